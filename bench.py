@@ -1,0 +1,181 @@
+"""Throughput of the FAMST hot path on one MI355X.
+
+One step = one full pass of the pipeline over the resident input: kNN graph
+(matrix-core screening + float32 re-rank) -> graph, components and
+lambda-edges -> refinement rounds -> spanning tree and its weight -> weight
+gradient.  The headline value is points/s of the bfloat16-screened path;
+the float32-screened path is timed beside it.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
+HBM_GBS = 8000.0
+
+# workload name -> (generator kwargs, k, lambda)
+WORKLOADS = {
+    "gamma-int-1m-d128": ("gamma_int", dict(n=1_000_000, d=128), 20, 10),
+    "blobs-10k-d32": ("blobs", dict(n=10_000, d=32), 10, 5),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_step(F, Xd, k, lam, seed, rounds, precision, exact, e_cap, gW):
+    out = F.famst(Xd, k, lam, seed=seed, max_rounds=rounds, precision=precision, exact=exact,
+                  e_cap=e_cap)
+    grad = F.mst_backward(Xd, out.tu, out.tv, gW)
+    return out, grad
+
+
+def time_path(F, torch, Xd, k, lam, seed, rounds, precision, exact, steps, warmup, profile):
+    gW = torch.ones(1, device=Xd.device)
+    e_cap = None
+    out = None
+    for _ in range(warmup):
+        out, _ = run_step(F, Xd, k, lam, seed, rounds, precision, exact, e_cap, gW)
+        e_cap = max(1, len(out.E))
+    torch.cuda.synchronize()
+    if profile:
+        F.profile_reset()
+        F.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, grad = run_step(F, Xd, k, lam, seed, rounds, precision, exact, e_cap, gW)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = {}
+    if profile:
+        F.profile_enable(False)
+        for name in ["prep", "dist_topk", "rerank", "exact_row", "sort", "scan", "graph_keys",
+                     "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
+                     "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]:
+            nl, ms = F.profile_read(name)
+            if nl:
+                phases[name] = {"launches": nl, "total_ms": round(ms, 3)}
+    return (t1 - t0) * 1000.0 / steps, out, phases
+
+
+def cpu_baseline(X, k, rows):
+    import oracle
+    t0 = time.perf_counter()
+    nbr, sq = oracle.knn_exact(X, k, rows=rows, block=64)
+    t1 = time.perf_counter()
+    return nbr, t1 - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gamma-int-1m-d128", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--rounds", type=int, default=10)
+    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in the design notes, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import datagen
+    import paper_2507_14261_amd as F
+
+    F.load()
+    gen_name, kw, k, lam = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    X = getattr(datagen, gen_name)(seed=0, **kw)
+    n, d = X.shape
+    log(f"generated {args.workload}: n={n} d={d} in {time.perf_counter() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to("cuda:0")
+    torch.cuda.synchronize()
+
+    ms_bf16, out_b, phases_b = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "bf16", False,
+                                         args.steps, args.warmup, True)
+    log(f"bf16 path: {ms_bf16:.1f} ms/step")
+    ms_fp32, out_f, phases_f = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "fp32", True,
+                                         args.fp32_steps, 1, True)
+    log(f"fp32 path: {ms_fp32:.1f} ms/step")
+    Wb = float(out_b.W[0].item())
+    Wf = float(out_f.W[0].item())
+
+    # roofline of the dominant kernel (distance tiles): 2 n^2 d flops per launch
+    flops = 2.0 * n * n * d
+    nl, tot = phases_b.get("dist_topk", {}).get("launches", 0), phases_b.get("dist_topk", {}).get("total_ms", 0.0)
+    avg_ms = tot / nl if nl else float("nan")
+    achieved = flops / (avg_ms * 1e-3) / 1e12 if nl else None
+    nlf, totf = phases_f.get("dist_topk", {}).get("launches", 0), phases_f.get("dist_topk", {}).get("total_ms", 0.0)
+    avg_f = totf / nlf if nlf else float("nan")
+
+    # sampled exact-kNN parity at full size + the CPU oracle baseline
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(n, size=args.cpu_rows, replace=False))
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        ref_nbr, t_cpu = cpu_baseline(X, k, rows)
+        nb_b = out_b.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
+        nb_f = out_f.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
+        rec_b = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_b, ref_nbr)]))
+        rec_f = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_f, ref_nbr)]))
+        parity = {"sample_rows": int(len(rows)), "recall_bf16": rec_b, "recall_fp32": rec_f}
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": round(len(rows) / t_cpu, 3), "unit": "points/s", "cores": cores, "kind": "oracle",
+               "sample": (f"exact float64 kNN (the oracle's Phase 1, the dominant phase) of {len(rows)} "
+                          f"query rows against all {n} points; {t_cpu:.1f} s")}
+
+    res = {
+        "metric": "points/s to approx MST at stated weight error, BF16/FP8+rerank vs FP32",
+        "value": round(n / (ms_bf16 * 1e-3), 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_bf16, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d, "k": k, "lambda": lam,
+                   "max_rounds": args.rounds, "seed": args.seed,
+                   "precision": "bf16 screening + fp32 re-rank", "components": out_b.graph.n_comp[0],
+                   "inter_component_edges": len(out_b.E), "refine_rounds": out_b.rounds},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
+                     "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["bf16"], 4) if achieved else None,
+                     "traffic": None, "kernel": "dist_topk", "avg_ms": round(avg_ms, 3),
+                     "algorithmic_flops": flops},
+        "cpu_baseline": cpu,
+        "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf},
+        "fp32_path": {"ms_per_step": round(ms_fp32, 3), "points_per_s": round(n / (ms_fp32 * 1e-3), 1),
+                      "dist_topk_avg_ms": round(avg_f, 3),
+                      "dist_topk_tflops": round(flops / (avg_f * 1e-3) / 1e12, 2) if nlf else None,
+                      "frac_of_fp32_peak": round(flops / (avg_f * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4) if nlf else None},
+        "phases_ms_bf16": phases_b,
+        "phases_ms_fp32": phases_f,
+        "parity": parity,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,116 @@
+// Gradient of the spanning-tree weight W = sum over tree edges of
+// |x_i - x_j| (the weight in Eq. (1)) with respect to the coordinates, the
+// tree held fixed: every edge adds its unit direction (x_i - x_j)/|x_i - x_j|
+// to row i and the opposite to row j.  Rows gather their incident edges in
+// ascending edge order, so the sums are deterministic.
+#include "famst_common.hpp"
+#include "prims.hpp"
+
+namespace famst {
+
+__global__ void incid_keys_kernel(const int32_t* __restrict__ tu, const int32_t* __restrict__ tv,
+                                  int64_t m, int64_t n, uint64_t* __restrict__ keys,
+                                  int64_t* __restrict__ deg, int* __restrict__ bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int64_t a = tu[e], b = tv[e];
+  if (a < 0 || a >= n || b < 0 || b >= n) {
+    atomicOr(bad, 1);
+    a = 0;
+    b = 0;
+  }
+  keys[2 * e] = ((uint64_t)a << 32) | (uint64_t)e;
+  keys[2 * e + 1] = ((uint64_t)b << 32) | (uint64_t)e;
+  atomicAdd(reinterpret_cast<unsigned long long*>(&deg[a]), 1ull);
+  atomicAdd(reinterpret_cast<unsigned long long*>(&deg[b]), 1ull);
+}
+
+// one 16-lane group per row
+__global__ __launch_bounds__(256) void tree_grad_kernel(const float* __restrict__ X, int d, int64_t n,
+                                                        const int64_t* __restrict__ offs, int B,
+                                                        const int32_t* __restrict__ tu,
+                                                        const int32_t* __restrict__ tv,
+                                                        const uint64_t* __restrict__ skeys,
+                                                        const int64_t* __restrict__ ptr,
+                                                        const float* __restrict__ gW,
+                                                        float* __restrict__ grad) {
+  const int64_t v = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int r16 = threadIdx.x & 15;
+  if (v >= n) return;
+  const float* xv = X + v * d;
+  const float g = gW[find_cloud(offs, B, v)];
+  const int64_t p0 = ptr[v], p1 = ptr[v + 1];
+  float* out = grad + v * d;
+  for (int t0 = 0; t0 < d; t0 += 16 * 8) {
+    float acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+      uint32_t e = (uint32_t)skeys[p];
+      int o = (tu[e] == v) ? tv[e] : tu[e];
+      const float* xo = X + (int64_t)o * d;
+      float s = sq32_group(xv, xo, d, r16);
+      if (s == 0.f) continue;
+      float w = __builtin_sqrtf(s);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int t = t0 + q * 16 + r16;
+        if (t < d) acc[q] += (xv[t] - xo[t]) / w;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int t = t0 + q * 16 + r16;
+      if (t < d) out[t] = g * acc[q];
+    }
+  }
+}
+
+}  // namespace famst
+
+using namespace famst;
+
+extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
+                                  int32_t B, const int32_t* tu, const int32_t* tv, const float* gW,
+                                  float* grad_X, void* ws, size_t* ws_bytes, void* stream) {
+  if (!ws_bytes) return FAMST_EINVAL;
+  if (n < 2 || d < 1 || B < 1) return FAMST_EINVAL;
+  if (n >= (int64_t(1) << 31)) return FAMST_EINVAL;
+  int64_t one[2] = {0, n};
+  const int64_t* offs = offs_h ? offs_h : one;
+  if (!offs_h && B != 1) return FAMST_EINVAL;
+  if (offs[0] != 0 || offs[B] != n) return FAMST_EINVAL;
+  for (int b = 0; b < B; ++b)
+    if (offs[b + 1] - offs[b] < 2) return FAMST_EINVAL;
+  const int64_t m = n - B;
+  Carve cv(ws);
+  uint64_t* keys = cv.take<uint64_t>(2 * m);
+  uint64_t* skeys = cv.take<uint64_t>(2 * m);
+  int64_t* deg = cv.take<int64_t>(n + 1);
+  int64_t* ptr = cv.take<int64_t>(n + 1);
+  int64_t* offs_d = cv.take<int64_t>(B + 1);
+  int* bad = cv.take<int>(1);
+  size_t tmpb = std::max(sort_keys_u64_bytes(2 * m), scan_i64_bytes(n + 1));
+  void* tmp = cv.take<char>(tmpb);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!X || !tu || !tv || !gW || !grad_X) return FAMST_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+  FAMST_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  FAMST_TRY(fill_i64(deg, 0, n + 1, s));
+  FAMST_TRY(launch("incid_keys", incid_keys_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, tu, tv, m, n,
+                   keys, deg, bad));
+  FAMST_TRY(sort_keys_u64(tmp, tmpb, keys, skeys, 2 * m, 64, s));
+  FAMST_TRY(exclusive_scan_i64(tmp, tmpb, deg, ptr, n + 1, s));
+  int hbad = 0;
+  FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipStreamSynchronize(s));
+  if (hbad) return FAMST_EINVAL;
+  FAMST_TRY(launch("mst_backward", tree_grad_kernel, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n,
+                   offs_d, B, tu, tv, skeys, ptr, gW, grad_X));
+  return FAMST_OK;
+}

@@ -1,0 +1,184 @@
+// Shared device helpers and host plumbing of libfamst (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/famst.h"
+
+namespace famst {
+
+// ---------------------------------------------------------------- types
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4;
+typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8;
+
+constexpr int WAVE = 64;
+constexpr float F_INF = __builtin_inff();
+
+// ------------------------------------------------------------ host status
+struct Status {
+  int code = FAMST_OK;
+};
+
+#define FAMST_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return FAMST_EHIP;              \
+  } while (0)
+
+#define FAMST_TRY(call)                                   \
+  do {                                                    \
+    int s_ = (call);                                      \
+    if (s_ < 0) return s_;                                \
+  } while (0)
+
+// Carves a caller-provided workspace.  Run once with base == nullptr to
+// compute the size, then with the real base.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t bytes() const { return (off + 255) & ~size_t(255); }
+};
+
+// ------------------------------------------------------------- profiling
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(hipStream_t s);
+
+template <class K, class... Args>
+inline int launch(const char* name, K kernel, dim3 grid, dim3 block, size_t lds,
+                  hipStream_t s, Args... args) {
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return FAMST_OK;
+  prof_begin(name, s);
+  hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  hipError_t e = hipGetLastError();
+  prof_end(s);
+  return e == hipSuccess ? FAMST_OK : FAMST_EHIP;
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long ballot(bool p) {
+  return __ballot(p);
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int readlane_i(int v, int l) {
+  return __builtin_amdgcn_readlane(v, l);
+}
+
+// Relative error bound of the float32 direct-difference squared distance
+// computed by sq32_group below: each of 16 lanes sums ceil(d/16) products
+// with fused multiply-adds, then 4 pairwise additions, and the differences
+// are rounded once.  Doubled for safety margin.
+__host__ __device__ inline float tau32(int d) {
+  int m = (d + 15) / 16;
+  return 2.0f * (float)(m + 4 + 2) * 5.9604645e-8f;  // 2^-24
+}
+
+// Canonical float32 squared distance by direct difference.  Evaluated by a
+// group of 16 consecutive lanes (r = lane within the group): lane r sums
+// dimensions r, r+16, r+32, ... with fmaf, then a fixed xor-butterfly over
+// the 16 lanes.  Every lane of the group returns the same bits, and
+// sq32(a, b) == sq32(b, a) exactly because (a-b)^2 == (b-a)^2.
+__device__ __forceinline__ float sq32_group(const float* __restrict__ a,
+                                            const float* __restrict__ b, int d, int r) {
+  float acc = 0.f;
+  for (int t = r; t < d; t += 16) {
+    float df = a[t] - b[t];
+    acc = __builtin_fmaf(df, df, acc);
+  }
+  acc += __shfl_xor(acc, 8, 16);
+  acc += __shfl_xor(acc, 4, 16);
+  acc += __shfl_xor(acc, 2, 16);
+  acc += __shfl_xor(acc, 1, 16);
+  return acc;
+}
+
+// float64 squared distance of the same pair (used only to order two
+// float32 values that are within rounding of each other).
+__device__ __forceinline__ double sq64_group(const float* __restrict__ a,
+                                             const float* __restrict__ b, int d, int r) {
+  double acc = 0.0;
+  for (int t = r; t < d; t += 16) {
+    double df = (double)a[t] - (double)b[t];
+    acc = __builtin_fma(df, df, acc);
+  }
+  acc += __shfl_xor(acc, 8, 16);
+  acc += __shfl_xor(acc, 4, 16);
+  acc += __shfl_xor(acc, 2, 16);
+  acc += __shfl_xor(acc, 1, 16);
+  return acc;
+}
+
+// (s, id) lexicographic order.
+__device__ __forceinline__ bool key_less(float s1, int i1, float s2, int i2) {
+  return s1 < s2 || (s1 == s2 && i1 < i2);
+}
+__device__ __forceinline__ bool key_less64(double s1, int i1, double s2, int i2) {
+  return s1 < s2 || (s1 == s2 && i1 < i2);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of the
+// two-multiplier S-box with a Weyl-sequence key schedule.
+struct U4 { uint32_t x, y, z, w; };
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    U4 o;
+    o.x = hi1 ^ c.y ^ k0;
+    o.y = lo1;
+    o.z = hi0 ^ c.w ^ k1;
+    o.w = lo0;
+    c = o;
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// (r * size) >> 32
+__device__ __forceinline__ uint32_t range_map(uint32_t r, uint32_t size) {
+  return __umulhi(r, size);
+}
+
+// IEEE float32 -> bfloat16 bits, round to nearest even (finite inputs).
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// Binary search: index b with offs[b] <= v < offs[b+1] (offs ascending).
+__device__ __forceinline__ int find_cloud(const int64_t* offs, int B, int64_t v) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace famst

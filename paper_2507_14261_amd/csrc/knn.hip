@@ -1,0 +1,560 @@
+// Phase 1 of FAMST (Alg. 1, GetANNs): exact k nearest neighbours by
+// matrix-core distance screening with a fused per-row top-k', float32
+// direct-difference re-ranking and exact recomputation of rows the
+// screening bound cannot certify.
+#include "famst_common.hpp"
+#include "select.hpp"
+
+namespace famst {
+
+// ------------------------------------------------------------------ prep
+// One wave per row: padded screening copy (float32 or bfloat16 RNE), its
+// squared norm, the norm of the quantisation error and a non-finite flag.
+// gstat[0] = non-finite flag, gstat[1] = max norm bits, gstat[2] = max
+// quantisation error bits (non-negative floats order like their bits).
+template <int PREC>
+__global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                   int DP, void* __restrict__ Xq,
+                                                   float* __restrict__ nq, float* __restrict__ qerr,
+                                                   unsigned* __restrict__ gstat) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float* x = X + row * d;
+  float acc = 0.f, eacc = 0.f;
+  bool bad = false;
+  for (int t = lane; t < DP; t += 64) {
+    float v = t < d ? x[t] : 0.f;
+    bad |= !__builtin_isfinite(v);
+    float q;
+    if (PREC == FAMST_FP32) {
+      q = v;
+      reinterpret_cast<float*>(Xq)[row * DP + t] = q;
+    } else {
+      uint16_t b = f32_to_bf16_rne(v);
+      q = bf16_to_f32(b);
+      reinterpret_cast<uint16_t*>(Xq)[row * DP + t] = b;
+    }
+    acc = __builtin_fmaf(q, q, acc);
+    float e = q - v;
+    eacc = __builtin_fmaf(e, e, eacc);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    acc += __shfl_xor(acc, o);
+    eacc += __shfl_xor(eacc, o);
+  }
+  unsigned long long anybad = ballot(bad);
+  if (lane == 0) {
+    nq[row] = acc;
+    // sqrt rounding and the float32 sum itself: inflate slightly
+    float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
+    qerr[row] = e;
+    if (anybad) atomicOr(&gstat[0], 1u);
+    atomicMax(&gstat[1], __float_as_uint(acc));
+    atomicMax(&gstat[2], __float_as_uint(e));
+  }
+}
+
+// ------------------------------------------------------ distance + top-k'
+// Work unit of one block: queries [q0, q1) of one cloud against the
+// cloud's rows [c0, c1).
+struct BlockDesc {
+  int q0, q1, c0, c1;
+};
+
+template <int PREC>
+struct Scr;
+template <>
+struct Scr<FAMST_FP32> {
+  using T = float;
+  static constexpr int KBW = 16;  // k covered by one 16-byte fragment per lane x 4 lane groups
+  static constexpr int ESZ = 4;
+};
+template <>
+struct Scr<FAMST_BF16> {
+  using T = uint16_t;
+  static constexpr int KBW = 32;
+  static constexpr int ESZ = 2;
+};
+
+// Squared-distance screening of 64*QB queries per wave (4 waves per block)
+// against 64-row tiles of the cloud, on the matrix cores:
+//   acc(j, q) = x_j . x_q   (16x16 output blocks, db rows x queries)
+//   s(j, q)   = |x_j|^2 + |x_q|^2 - 2 acc
+// Each wave keeps, for each of its queries, the KC smallest (s, j) in an
+// LDS list sorted ascending; a tile element reaches the insertion path only
+// if s is within the list's current maximum.
+template <int PREC, int NKB, int QB, int KC>
+__global__ __launch_bounds__(256, 1) void dist_topk_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, int DP, int nkb,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s) {
+  using S = Scr<PREC>;
+  using T = typename S::T;
+  constexpr int QW = 16 * QB;           // queries per wave
+  constexpr int QBLK = 4 * QW;          // queries per block
+  constexpr int BN = 64;                // tile rows
+  const T* Xq = reinterpret_cast<const T*>(Xq_);
+
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float* ls = reinterpret_cast<float*>(smem);               // [QBLK][KC]
+  int* lj = reinterpret_cast<int*>(ls + QBLK * KC);         // [QBLK][KC]
+  char* tile = reinterpret_cast<char*>(lj + QBLK * KC);     // [BN][RS]
+  const int RS = DP * S::ESZ + 16;                          // padded row stride (bytes)
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;   // first query of this wave
+
+  // lists start as (+inf, INT_MAX)
+  for (int e = tid; e < QBLK * KC; e += 256) {
+    ls[e] = F_INF;
+    lj[e] = 0x7FFFFFFF;
+  }
+
+  // resident query fragments
+  i32x4 qf[QB][NKB];
+  float nqq[QB], U[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    int q = wq0 + qb * 16 + i16;
+    bool ok = q < bd.q1;
+    nqq[qb] = ok ? nq[q] : 0.f;
+    U[qb] = ok ? F_INF : -F_INF;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      i32x4 v = {0, 0, 0, 0};
+      if (ok && kb < nkb) {
+        const char* p = reinterpret_cast<const char*>(Xq + (int64_t)q * DP) +
+                        (kb * S::KBW + g * (S::KBW / 4)) * S::ESZ;
+        v = *reinterpret_cast<const i32x4*>(p);
+      }
+      qf[qb][kb] = v;
+    }
+  }
+  __syncthreads();
+
+  const int cpr = DP * S::ESZ / 16;     // 16-byte chunks per row
+  const int nchunk = BN * cpr;
+
+  for (int t0 = bd.c0; t0 < bd.c1; t0 += BN) {
+    // ---- stage tile rows [t0, t0+64) into LDS
+    for (int c = tid; c < nchunk; c += 256) {
+      int r = c / cpr, cc = c - r * cpr;
+      int row = t0 + r;
+      i32x4 v = {0, 0, 0, 0};
+      if (row < bd.c1)
+        v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(Xq + (int64_t)row * DP) + cc * 16);
+      *reinterpret_cast<i32x4*>(tile + r * RS + cc * 16) = v;
+    }
+    __syncthreads();
+
+    // ---- matrix-core products
+    f32x4 acc[QB][4];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb < nkb) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+          i32x4 a = *reinterpret_cast<const i32x4*>(
+              tile + (jb * 16 + i16) * RS + (kb * S::KBW + g * (S::KBW / 4)) * S::ESZ);
+#pragma unroll
+          for (int qb = 0; qb < QB; ++qb) {
+            if constexpr (PREC == FAMST_FP32) {
+              f32x4 af = __builtin_bit_cast(f32x4, a);
+              f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+              acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
+              acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
+              acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
+              acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
+            } else {
+              bf16x8 af = __builtin_bit_cast(bf16x8, a);
+              bf16x8 bf = __builtin_bit_cast(bf16x8, qf[qb][kb]);
+              acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[qb][jb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+
+    // ---- screening filter: lane holds rows t0 + jb*16 + 4g + r, query qb*16 + i16
+    float nqj[4][4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = t0 + jb * 16 + 4 * g + r;
+        nqj[jb][r] = row < bd.c1 ? nq[row] : F_INF;
+      }
+    bool any = false;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      float m = F_INF;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m = fminf(m, __builtin_fmaf(-2.f, acc[qb][jb][r], nqj[jb][r]));
+      any |= m <= U[qb];
+    }
+    if (ballot(any)) {
+      // insertion path: visit passing elements one at a time (wave-uniform)
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float sp = __builtin_fmaf(-2.f, acc[qb][jb][r], nqj[jb][r]);
+            unsigned long long mask = ballot(sp <= U[qb]);
+            while (mask) {
+              int src = __builtin_ctzll(mask);
+              mask &= mask - 1;
+              int qi = qb * 16 + (src & 15);                    // query within wave
+              int j = t0 + jb * 16 + 4 * (src >> 4) + r;         // candidate row
+              int q = wq0 + qi;
+              float s = readlane_f(sp, src) + readlane_f(nqq[qb], src);
+              if (j >= bd.c1 || j == q) continue;
+              volatile float* L = ls + (wave * QW + qi) * KC;
+              volatile int* J = lj + (wave * QW + qi) * KC;
+              float cs = lane < KC ? L[lane] : F_INF;
+              int cj = lane < KC ? J[lane] : 0x7FFFFFFF;
+              bool lt = lane < KC && key_less(cs, cj, s, j);
+              int pos = __builtin_popcountll(ballot(lt));
+              if (pos >= KC) continue;
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              if (lane >= pos && lane < KC - 1) {
+                L[lane + 1] = cs;
+                J[lane + 1] = cj;
+              }
+              if (lane == pos) {
+                L[lane] = s;
+                J[lane] = j;
+              }
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              float Tn = (pos == KC - 1) ? s : readlane_f(cs, KC - 2);
+              // a few ulps of slack so rounding in U never hides an equal key
+              float Un = Tn - nqq[qb];
+              Un = Un + fabsf(Tn) * 2.4e-7f;
+              if (i16 == (src & 15)) U[qb] = Un;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write the candidate lists
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    for (int qq = 0; qq < 16; ++qq) {
+      int qi = qb * 16 + qq;
+      int q = wq0 + qi;
+      if (q < bd.q1 && lane < KC) {
+        cand_s[(int64_t)q * KC + lane] = ls[(wave * QW + qi) * KC + lane];
+        cand_j[(int64_t)q * KC + lane] = lj[(wave * QW + qi) * KC + lane];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- re-rank
+// One wave per row: direct-difference float32 distances of the KC
+// candidates, selection of the k smallest by (s, j) with float64 at a
+// near-tie boundary, and the certificate that no non-candidate is closer.
+struct RerankArgs {
+  const float* X;
+  int64_t n;
+  int d;
+  const int64_t* offs;
+  int B;
+  int k, KC;
+  const int* cand_j;
+  const float* cand_s;
+  const float* nq;
+  const float* qerr;
+  const unsigned* gstat;
+  float arith_c;          // screening arithmetic error factor (x 2^-24 folded in)
+  int* nbr;
+  float* dist;
+  float* kth_s;           // s of the k-th selected (for recomputation)
+  int* bad_rows;          // rows not certified
+  unsigned long long* counters;  // [0] not certified, [1] recomputed, [2] near ties
+};
+
+__global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
+  __shared__ SelectSmem<64> sm;
+  const int64_t q = blockIdx.x;
+  const int t = threadIdx.x;
+  const int cb = find_cloud(a.offs, a.B, q);
+  const int64_t nb = a.offs[cb + 1] - a.offs[cb];
+  const int L = (int)min<int64_t>(a.KC, nb - 1);
+  const float* xq = a.X + q * a.d;
+  const float tau = tau32(a.d);
+  if (t < L) sm.id[t] = a.cand_j[q * a.KC + t];
+  __syncthreads();
+  const int grp = t >> 4, r16 = t & 15;
+  for (int c = grp; c < L; c += 4) {
+    float v = sq32_group(xq, a.X + (int64_t)sm.id[c] * a.d, a.d, r16);
+    if (r16 == 0) sm.s[c] = v;
+  }
+  __syncthreads();
+  bool tie = block_select<64, 64>(sm, L, a.k, tau, a.d, [&](int i, const float** pa, const float** pb) {
+    *pa = xq;
+    *pb = a.X + (int64_t)sm.id[i] * a.d;
+  });
+  float kth = 0.f;
+  if (t < L && sm.pos[t] >= 0) {
+    a.nbr[q * a.k + sm.pos[t]] = sm.id[t];
+    a.dist[q * a.k + sm.pos[t]] = __builtin_sqrtf(sm.s[t]);
+    kth = sm.s[t];
+  }
+  for (int o = 32; o >= 1; o >>= 1) kth = fmaxf(kth, __shfl_xor(kth, o));
+  if (t == 0) {
+    a.kth_s[q] = kth;
+    if (tie) atomicAdd(&a.counters[2], 1ull);
+    bool cert = true;
+    if (nb - 1 > a.KC) {
+      // every non-candidate j has screened value >= S' (the list maximum)
+      float Sp = a.cand_s[q * a.KC + a.KC - 1];
+      float nmax = __uint_as_float(a.gstat[1]);
+      float emax = __uint_as_float(a.gstat[2]);
+      float eps = a.arith_c * (a.nq[q] + nmax);
+      float lb_scr = Sp - eps;
+      float root = lb_scr > 0.f ? __builtin_sqrtf(lb_scr) * (1.0f - 1e-6f) : 0.f;
+      float rr = root - (a.qerr[q] + emax);
+      float lb = rr > 0.f ? rr * rr * (1.0f - 1e-6f) : 0.f;
+      cert = lb > kth * (1.0f + 2.0f * tau);
+    }
+    if (!cert) {
+      unsigned long long p = atomicAdd(&a.counters[0], 1ull);
+      a.bad_rows[p] = (int)q;
+    }
+  }
+}
+
+// Exact recomputation of a row: collect every point whose float32 distance
+// is within the bound of the current k-th, then select as above.
+constexpr int FB_CAP = 2048;
+
+__global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict__ X, int d,
+                                                        const int64_t* __restrict__ offs, int B,
+                                                        int k, const int* __restrict__ rows,
+                                                        const float* __restrict__ kth_s,
+                                                        int* __restrict__ nbr, float* __restrict__ dist,
+                                                        unsigned long long* __restrict__ counters,
+                                                        int* __restrict__ overflow) {
+  __shared__ SelectSmem<FB_CAP> sm;
+  __shared__ int cnt;
+  const int64_t q = rows[blockIdx.x];
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  const int cb = find_cloud(offs, B, q);
+  const int64_t c0 = offs[cb], c1 = offs[cb + 1];
+  const float tau = tau32(d);
+  const float T = kth_s[q] * (1.0f + 2.0f * tau) * (1.0f + 2.0f * tau);
+  const float* xq = X + q * d;
+  if (t == 0) cnt = 0;
+  __syncthreads();
+  for (int64_t j0 = c0; j0 < c1; j0 += 16) {
+    int64_t j = j0 + grp;
+    float v = F_INF;
+    if (j < c1 && j != q) v = sq32_group(xq, X + j * d, d, r16);
+    if (r16 == 0 && v <= T) {
+      int p = atomicAdd(&cnt, 1);
+      if (p < FB_CAP) {
+        sm.s[p] = v;
+        sm.id[p] = (int)j;
+      }
+    }
+  }
+  __syncthreads();
+  const int L = cnt;
+  if (L > FB_CAP) {
+    if (t == 0) atomicOr(overflow, 1);
+    return;
+  }
+  block_select<256, FB_CAP>(sm, L, k, tau, d, [&](int i, const float** pa, const float** pb) {
+    *pa = xq;
+    *pb = X + (int64_t)sm.id[i] * d;
+  });
+  for (int i = t; i < L; i += 256) {
+    if (sm.pos[i] >= 0) {
+      nbr[q * k + sm.pos[i]] = sm.id[i];
+      dist[q * k + sm.pos[i]] = __builtin_sqrtf(sm.s[i]);
+    }
+  }
+  if (t == 0) atomicAdd(&counters[1], 1ull);
+}
+
+// --------------------------------------------------------------- host side
+struct KnnPlan {
+  int prec, KC, DP, nkb, QB, qblk;
+  size_t lds;
+};
+
+static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
+  p.prec = prec;
+  p.KC = k_cand ? k_cand : (k <= 24 ? 32 : 64);
+  if (p.KC != 32 && p.KC != 64) return FAMST_EINVAL;
+  if (p.KC < k) return FAMST_EINVAL;
+  const int kbw = prec == FAMST_FP32 ? 16 : 32;
+  p.nkb = (d + kbw - 1) / kbw;
+  p.DP = p.nkb * kbw;
+  const int nkb_max = prec == FAMST_FP32 ? 8 : 8;
+  if (p.nkb > nkb_max) return FAMST_ENOTIMPL;
+  p.QB = (p.KC == 64) ? 2 : 4;
+  p.qblk = 64 * p.QB;
+  const int esz = prec == FAMST_FP32 ? 4 : 2;
+  p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * (p.DP * esz + 16);
+  if (p.lds > 160 * 1024) return FAMST_ENOTIMPL;
+  return FAMST_OK;
+}
+
+template <int PREC, int NKB, int QB, int KC>
+static int launch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                     const BlockDesc* desc, int* cj, float* cs) {
+  auto kern = dist_topk_kernel<PREC, NKB, QB, KC>;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.DP, p.nkb, desc,
+                cj, cs);
+}
+
+template <int PREC>
+static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                       const BlockDesc* desc, int* cj, float* cs) {
+#define DT_CASE(NKB)                                                                        \
+  if (p.nkb <= NKB) {                                                                       \
+    if (p.KC == 32) return launch_dt<PREC, NKB, 4, 32>(p, nblk, s, Xq, nq, desc, cj, cs);   \
+    return launch_dt<PREC, NKB, 2, 64>(p, nblk, s, Xq, nq, desc, cj, cs);                   \
+  }
+  DT_CASE(1)
+  DT_CASE(2)
+  DT_CASE(4)
+  DT_CASE(8)
+#undef DT_CASE
+  return FAMST_ENOTIMPL;
+}
+
+}  // namespace famst
+
+using namespace famst;
+
+extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
+                               int32_t B, int32_t k, int32_t precision, int32_t k_cand,
+                               int32_t* nbr, float* dist, int64_t* stats, void* ws,
+                               size_t* ws_bytes, void* stream) {
+  if (!ws_bytes) return FAMST_EINVAL;
+  if (n < 2 || d < 1 || k < 1 || k > 64 || B < 1) return FAMST_EINVAL;
+  const int prec = precision & 0xFF;
+  const bool exact = (precision & FAMST_EXACT) != 0;
+  if ((precision & ~(0xFF | FAMST_EXACT)) != 0) return FAMST_EINVAL;
+  if (prec != FAMST_FP32 && prec != FAMST_BF16 && prec != FAMST_FP8_E4M3) return FAMST_EINVAL;
+  if (prec == FAMST_FP8_E4M3) return FAMST_ENOTIMPL;
+  int64_t one[2] = {0, n};
+  const int64_t* offs = offs_h ? offs_h : one;
+  if (!offs_h && B != 1) return FAMST_EINVAL;
+  if (offs[0] != 0 || offs[B] != n) return FAMST_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    int64_t nb = offs[b + 1] - offs[b];
+    if (nb < 2 || k > nb - 1) return FAMST_EINVAL;
+  }
+  if (n >= (int64_t(1) << 31)) return FAMST_EINVAL;
+  KnnPlan p;
+  FAMST_TRY(choose_plan(prec, d, k, k_cand, p));
+  int nblk = 0;
+  for (int b = 0; b < B; ++b) nblk += (int)cdiv(offs[b + 1] - offs[b], p.qblk);
+  const int esz = prec == FAMST_FP32 ? 4 : 2;
+
+  Carve cv(ws);
+  void* Xq = cv.take<char>((size_t)n * p.DP * esz);
+  float* nq = cv.take<float>(n);
+  float* qerr = cv.take<float>(n);
+  unsigned* gstat = cv.take<unsigned>(4);
+  BlockDesc* desc = cv.take<BlockDesc>(nblk);
+  int64_t* offs_d = cv.take<int64_t>(B + 1);
+  int* cj = cv.take<int>((size_t)n * p.KC);
+  float* cs = cv.take<float>((size_t)n * p.KC);
+  float* kth = cv.take<float>(n);
+  int* bad = cv.take<int>(n);
+  unsigned long long* ctr = cv.take<unsigned long long>(4);
+  int* ovf = cv.take<int>(1);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!X || !nbr || !dist) return FAMST_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // block descriptors and offsets (host -> device)
+  BlockDesc* hd = new BlockDesc[nblk];
+  int bi = 0;
+  for (int b = 0; b < B; ++b)
+    for (int64_t q0 = offs[b]; q0 < offs[b + 1]; q0 += p.qblk)
+      hd[bi++] = BlockDesc{(int)q0, (int)offs[b + 1], (int)offs[b], (int)offs[b + 1]};
+  hipError_t e1 = hipMemcpyAsync(desc, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s);
+  hipError_t e2 = hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s);
+  hipError_t e3 = hipMemsetAsync(gstat, 0, 16, s);
+  hipError_t e4 = hipMemsetAsync(ctr, 0, 32, s);
+  hipError_t e6 = hipMemsetAsync(ovf, 0, sizeof(int), s);
+  hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
+  delete[] hd;
+  if (e1 || e2 || e3 || e4 || e5 || e6) return FAMST_EHIP;
+
+  if (prec == FAMST_FP32)
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_FP32>, dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, d,
+                     p.DP, Xq, nq, qerr, gstat));
+  else
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_BF16>, dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, d,
+                     p.DP, Xq, nq, qerr, gstat));
+  unsigned bad_flag = 0;
+  FAMST_HIP(hipMemcpyAsync(&bad_flag, gstat, 4, hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipStreamSynchronize(s));
+  if (bad_flag) return FAMST_ENONFINITE;
+
+  if (prec == FAMST_FP32)
+    FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs));
+  else
+    FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs));
+
+  RerankArgs ra;
+  ra.X = X; ra.n = n; ra.d = d; ra.offs = offs_d; ra.B = B; ra.k = k; ra.KC = p.KC;
+  ra.cand_j = cj; ra.cand_s = cs; ra.nq = nq; ra.qerr = qerr; ra.gstat = gstat;
+  // matrix-core dot products and norms: |err| <= (2d + 8) 2^-24 (|x|^2 + |y|^2)
+  ra.arith_c = (float)(2 * p.DP + 8) * 5.9604645e-8f;
+  ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_rows = bad; ra.counters = ctr;
+  FAMST_TRY(launch("rerank", rerank_kernel, dim3((unsigned)n), dim3(64), 0, s, ra));
+
+  unsigned long long hc[4] = {0, 0, 0, 0};
+  if (exact || stats) {
+    FAMST_HIP(hipMemcpyAsync(hc, ctr, 32, hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipStreamSynchronize(s));
+  }
+  if (exact && hc[0] > 0) {
+    FAMST_TRY(launch("exact_row", exact_row_kernel, dim3((unsigned)hc[0]), dim3(256), 0, s, X, d,
+                     offs_d, B, k, bad, kth, nbr, dist, ctr, ovf));
+    int hov = 0;
+    FAMST_HIP(hipMemcpyAsync(hc, ctr, 32, hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipMemcpyAsync(&hov, ovf, 4, hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipStreamSynchronize(s));
+    if (hov) return FAMST_ECAPACITY;
+  }
+  if (stats) {
+    for (int i = 0; i < FAMST_NSTATS; ++i) stats[i] = 0;
+    stats[FAMST_STAT_UNCERTIFIED] = (int64_t)hc[0];
+    stats[FAMST_STAT_RECOMPUTED] = (int64_t)hc[1];
+    stats[FAMST_STAT_NEAR_TIES] = (int64_t)hc[2];
+    stats[FAMST_STAT_K_CAND] = p.KC;
+  }
+  return FAMST_OK;
+}

@@ -1,0 +1,466 @@
+// Phase 4 of FAMST (Alg. 1, GetMST): the spanning tree of the kNN edges and
+// the refined inter-component edges.  Edges are keyed by (w, min, max);
+// under that strict order the minimum spanning tree is unique, so Boruvka
+// (Sec. 2.1) and Kruskal (Sec. 2.1, the paper's choice) give the same tree.
+// Also the exact tree of the complete graph by Prim (Sec. 2.1) for k = n-1.
+#include <vector>
+
+#include "famst_common.hpp"
+#include "prims.hpp"
+
+namespace famst {
+
+constexpr uint64_t KEY_NONE = ~uint64_t(0);
+
+// (min << 32 | max) keys with the weight bits as value; invalid entries are
+// flagged, self-loops become KEY_NONE (sorted last, dropped).
+__global__ void mst_keys_kernel(const int32_t* __restrict__ nbr, const float* __restrict__ dist,
+                                int64_t n, int k, const int32_t* __restrict__ eu,
+                                const int32_t* __restrict__ ev, const float* __restrict__ ew,
+                                int64_t ne, const int64_t* __restrict__ offs, int B,
+                                uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                int* __restrict__ bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nk = n * k;
+  if (e >= nk + ne) return;
+  int64_t a, b;
+  float w;
+  if (e < nk) {
+    a = e / k;
+    b = nbr[e];
+    w = dist[e];
+  } else {
+    a = eu[e - nk];
+    b = ev[e - nk];
+    w = ew[e - nk];
+  }
+  bool ok = a >= 0 && a < n && b >= 0 && b < n && w >= 0.f && __builtin_isfinite(w);
+  if (ok && B > 1) ok = find_cloud(offs, B, a) == find_cloud(offs, B, b);
+  if (!ok) atomicOr(bad, 1);
+  if (!ok || a == b) {
+    keys[e] = KEY_NONE;
+    vals[e] = 0;
+    return;
+  }
+  int64_t lo = min(a, b), hi = max(a, b);
+  keys[e] = ((uint64_t)lo << 32) | (uint64_t)hi;
+  vals[e] = __float_as_uint(w + 0.0f);  // -0 -> +0
+}
+
+__global__ void edge_unique_kernel(const uint64_t* __restrict__ keys, int64_t m,
+                                   int64_t* __restrict__ flag) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  uint64_t kk = keys[p];
+  bool keep = kk != KEY_NONE && (p == 0 || keys[p - 1] != kk);
+  flag[p] = keep ? 1 : 0;
+}
+
+__global__ void edge_compact_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                    const int64_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                                    int64_t m, int32_t* __restrict__ elo, int32_t* __restrict__ ehi,
+                                    uint32_t* __restrict__ ewb) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m || !flag[p]) return;
+  int64_t o = pos[p];
+  elo[o] = (int32_t)(keys[p] >> 32);
+  ehi[o] = (int32_t)(uint32_t)keys[p];
+  ewb[o] = vals[p];
+}
+
+// ------------------------------------------------------------- Boruvka
+__global__ void bv_min_edge_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
+                                   const uint32_t* __restrict__ ewb, int64_t m,
+                                   const int32_t* __restrict__ comp, unsigned long long* __restrict__ best) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int cu = comp[elo[e]], cv = comp[ehi[e]];
+  if (cu == cv) return;
+  unsigned long long key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
+  atomicMin(&best[cu], key);
+  atomicMin(&best[cv], key);
+}
+
+__global__ void bv_hook_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
+                               int64_t n, const int32_t* __restrict__ comp,
+                               const unsigned long long* __restrict__ best, int32_t* __restrict__ P,
+                               uint8_t* __restrict__ in_tree, int* __restrict__ hooked) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  if (comp[c] != c) return;
+  unsigned long long key = best[c];
+  if (key == ~0ull) {
+    P[c] = (int32_t)c;
+    return;
+  }
+  uint32_t e = (uint32_t)key;
+  int cl = comp[elo[e]], ch = comp[ehi[e]];
+  int other = (cl == c) ? ch : cl;
+  if (best[other] == key && c < other) {
+    P[c] = (int32_t)c;   // the smaller root of a mutual pair stays
+  } else {
+    P[c] = other;
+    in_tree[e] = 1;
+    *hooked = 1;
+  }
+}
+
+__global__ void bv_jump_kernel(const int32_t* __restrict__ comp, int64_t n, int32_t* P) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || comp[c] != c) return;
+  while (true) {
+    int p = __hip_atomic_load(&P[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int pp = __hip_atomic_load(&P[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == pp) break;
+    __hip_atomic_store(&P[c], pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void bv_relabel_kernel(int32_t* __restrict__ comp, const int32_t* __restrict__ P, int64_t n) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  comp[v] = P[comp[v]];
+}
+
+// ------------------------------------------------------------- Kruskal
+__global__ void kr_keys_kernel(const uint32_t* __restrict__ ewb, int64_t m, uint64_t* __restrict__ keys) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) keys[e] = ((uint64_t)ewb[e] << 32) | (uint64_t)e;
+}
+
+__device__ int kr_find(int32_t* parent, int x) {
+  while (parent[x] != x) {
+    parent[x] = parent[parent[x]];
+    x = parent[x];
+  }
+  return x;
+}
+
+// sequential union-find scan over the sorted keys (single thread)
+__global__ void kr_scan_kernel(const uint64_t* __restrict__ skeys, int64_t m,
+                               const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
+                               int32_t* parent, int64_t target, uint8_t* __restrict__ in_tree) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < m && cnt < target; ++i) {
+    uint32_t e = (uint32_t)skeys[i];
+    int a = kr_find(parent, elo[e]), b = kr_find(parent, ehi[e]);
+    if (a == b) continue;
+    if (a < b) parent[b] = a; else parent[a] = b;
+    in_tree[e] = 1;
+    ++cnt;
+  }
+}
+
+// ------------------------------------------------------------ tree output
+__global__ void u8_to_i64_kernel(const uint8_t* __restrict__ f, int64_t m, int64_t* __restrict__ o) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m) o[p] = f[p];
+  if (p == m) o[p] = 0;
+}
+
+__global__ void tree_compact_kernel(const uint8_t* __restrict__ in_tree, const int64_t* __restrict__ pos,
+                                    int64_t m, const int32_t* __restrict__ elo,
+                                    const int32_t* __restrict__ ehi, const uint32_t* __restrict__ ewb,
+                                    int32_t* __restrict__ tu, int32_t* __restrict__ tv,
+                                    float* __restrict__ tw) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m || !in_tree[p]) return;
+  int64_t o = pos[p];
+  tu[o] = elo[p];
+  tv[o] = ehi[p];
+  tw[o] = __uint_as_float(ewb[p]);
+}
+
+// Per-cloud tree weight: compensated (Neumaier) partial sums in a fixed
+// thread order, combined by a fixed tree of error-free additions.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ __launch_bounds__(256) void tree_weight_kernel(const float* __restrict__ tw,
+                                                          const int64_t* __restrict__ offs,
+                                                          float* __restrict__ W) {
+  __shared__ float ss[256], ee[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t e0 = offs[b] - b, e1 = offs[b + 1] - b - 1;
+  float s = 0.f, c = 0.f;
+  for (int64_t i = e0 + t; i < e1; i += 256) {
+    float x = tw[i], ns, err;
+    two_sum(s, x, ns, err);
+    s = ns;
+    c += err;
+  }
+  ss[t] = s;
+  ee[t] = c;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) {
+      float ns, err;
+      two_sum(ss[t], ss[t + w], ns, err);
+      ss[t] = ns;
+      ee[t] = ee[t] + ee[t + w] + err;
+    }
+    __syncthreads();
+  }
+  if (t == 0) W[b] = ss[0] + ee[0];
+}
+
+// ------------------------------------------------------------ dense Prim
+// Exact tree of the complete graph of one cloud per block: the
+// distances to the newest tree vertex are computed on the fly, so nothing
+// of size n^2 is stored.  Keys are (w, min, max) as everywhere.
+constexpr int PRIM_MAX = 16384;
+
+__device__ __forceinline__ bool ekey_less(float w1, int a1, int b1, float w2, int a2, int b2) {
+  int l1 = min(a1, b1), h1 = max(a1, b1), l2 = min(a2, b2), h2 = max(a2, b2);
+  if (w1 != w2) return w1 < w2;
+  if (l1 != l2) return l1 < l2;
+  return h1 < h2;
+}
+
+__global__ __launch_bounds__(256) void prim_kernel(const float* __restrict__ X, int d,
+                                                   const int64_t* __restrict__ offs,
+                                                   int32_t* __restrict__ ou, int32_t* __restrict__ ov,
+                                                   float* __restrict__ ow) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int b = blockIdx.x, t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  const int64_t c0 = offs[b];
+  const int nb = (int)(offs[b + 1] - c0);
+  float* bw = reinterpret_cast<float*>(smem);          // best weight to the tree
+  int* bf = reinterpret_cast<int*>(bw + PRIM_MAX);     // its tree endpoint (local), -1: in tree
+  __shared__ float rw[256];
+  __shared__ int rj[256];
+  __shared__ int cur_s;
+  for (int j = t; j < nb; j += 256) {
+    bw[j] = F_INF;
+    bf[j] = -2;   // -2: not reached yet
+  }
+  __syncthreads();
+  if (t == 0) {
+    bf[0] = -1;
+    cur_s = 0;
+  }
+  __syncthreads();
+  const int64_t eo = c0 - b;  // output slot of this cloud's first edge
+  for (int step = 1; step < nb; ++step) {
+    const int cur = cur_s;
+    const float* xc = X + (c0 + cur) * d;
+    for (int j = grp; j < nb; j += 16) {
+      if (bf[j] == -1) continue;  // uniform in group
+      float s = sq32_group(xc, X + (c0 + j) * d, d, r16);
+      float w = __builtin_sqrtf(s);
+      if (r16 == 0) {
+        int f = bf[j];
+        if (f == -2 || ekey_less(w, cur, j, bw[j], f, j)) {
+          bw[j] = w;
+          bf[j] = cur;
+        }
+      }
+    }
+    __syncthreads();
+    float mw = F_INF;
+    int mj = -1;
+    for (int j = t; j < nb; j += 256) {
+      if (bf[j] < 0) continue;
+      if (mj < 0 || ekey_less(bw[j], bf[j], j, mw, bf[mj], mj)) {
+        mw = bw[j];
+        mj = j;
+      }
+    }
+    rw[t] = mw;
+    rj[t] = mj;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (t < w) {
+        int oj = rj[t + w];
+        if (oj >= 0 && (rj[t] < 0 || ekey_less(rw[t + w], bf[oj], oj, rw[t], bf[rj[t]], rj[t]))) {
+          rw[t] = rw[t + w];
+          rj[t] = oj;
+        }
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      int j = rj[0];
+      int f = bf[j];
+      int lo = min(f, j), hi = max(f, j);
+      ou[eo + step - 1] = (int32_t)(c0 + lo);
+      ov[eo + step - 1] = (int32_t)(c0 + hi);
+      ow[eo + step - 1] = rw[0];
+      bf[j] = -1;
+      cur_s = j;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void pair_keys_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
+                                 const float* __restrict__ w, int64_t m, uint64_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  keys[e] = ((uint64_t)(uint32_t)a[e] << 32) | (uint32_t)b[e];
+  vals[e] = __float_as_uint(w[e]);
+}
+
+__global__ void unpack_tree_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                   int64_t m, int32_t* __restrict__ tu, int32_t* __restrict__ tv,
+                                   float* __restrict__ tw) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  tu[e] = (int32_t)(keys[e] >> 32);
+  tv[e] = (int32_t)(uint32_t)keys[e];
+  tw[e] = __uint_as_float(vals[e]);
+}
+
+}  // namespace famst
+
+using namespace famst;
+
+extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* offs_h, int32_t B,
+                         const int32_t* nbr, const float* dist, int32_t k, const int32_t* eu,
+                         const int32_t* ev, const float* ew, int64_t n_edges, int32_t algo,
+                         int32_t* tu, int32_t* tv, float* tw, float* W, void* ws, size_t* ws_bytes,
+                         void* stream) {
+  if (!ws_bytes) return FAMST_EINVAL;
+  if (n < 2 || B < 1 || k < 0 || n_edges < 0) return FAMST_EINVAL;
+  if (algo != FAMST_BORUVKA && algo != FAMST_KRUSKAL && algo != FAMST_DENSE_PRIM) return FAMST_EINVAL;
+  if (n >= (int64_t(1) << 31)) return FAMST_EINVAL;
+  int64_t one[2] = {0, n};
+  const int64_t* offs = offs_h ? offs_h : one;
+  if (!offs_h && B != 1) return FAMST_EINVAL;
+  if (offs[0] != 0 || offs[B] != n) return FAMST_EINVAL;
+  int64_t nbmax = 0;
+  for (int b = 0; b < B; ++b) {
+    int64_t nb = offs[b + 1] - offs[b];
+    if (nb < 2) return FAMST_EINVAL;
+    nbmax = std::max(nbmax, nb);
+  }
+  const int64_t nt = n - B;  // tree edges
+  Carve cv(ws);
+  int64_t* offs_d = cv.take<int64_t>(B + 1);
+  int* bad = cv.take<int>(2);
+  if (algo == FAMST_DENSE_PRIM) {
+    if (d < 1) return FAMST_EINVAL;
+    if (nbmax > PRIM_MAX) return FAMST_ENOTIMPL;
+    int32_t* pu = cv.take<int32_t>(nt);
+    int32_t* pv = cv.take<int32_t>(nt);
+    float* pw = cv.take<float>(nt);
+    uint64_t* k1 = cv.take<uint64_t>(nt);
+    uint64_t* k2 = cv.take<uint64_t>(nt);
+    uint32_t* v1 = cv.take<uint32_t>(nt);
+    uint32_t* v2 = cv.take<uint32_t>(nt);
+    size_t tmpb = sort_pairs_u64_u32_bytes(nt);
+    void* tmp = cv.take<char>(tmpb);
+    if (!ws) {
+      *ws_bytes = cv.bytes();
+      return FAMST_OK;
+    }
+    if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+    if (!X || !tu || !tv || !tw || !W) return FAMST_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+    static bool attr = false;
+    if (!attr) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(prim_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PRIM_MAX * 4);
+      attr = true;
+    }
+    FAMST_TRY(launch("dense_prim", prim_kernel, dim3(B), dim3(256), (size_t)2 * PRIM_MAX * 4, s, X, d,
+                     offs_d, pu, pv, pw));
+    FAMST_TRY(launch("pair_keys", pair_keys_kernel, dim3(cdiv(nt, 256)), dim3(256), 0, s, pu, pv, pw,
+                     nt, k1, v1));
+    FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, k1, k2, v1, v2, nt, 32 + bits_for(n), s));
+    FAMST_TRY(launch("unpack_tree", unpack_tree_kernel, dim3(cdiv(nt, 256)), dim3(256), 0, s, k2, v2,
+                     nt, tu, tv, tw));
+    FAMST_TRY(launch("tree_weight", tree_weight_kernel, dim3(B), dim3(256), 0, s, tw, offs_d, W));
+    return FAMST_OK;
+  }
+
+  const int64_t m0 = n * (int64_t)k + n_edges;
+  uint64_t* keys = cv.take<uint64_t>(m0);
+  uint64_t* skeys = cv.take<uint64_t>(m0);
+  uint32_t* vals = cv.take<uint32_t>(m0);
+  uint32_t* svals = cv.take<uint32_t>(m0);
+  int64_t* flag = cv.take<int64_t>(m0 + 1);
+  int64_t* pos = cv.take<int64_t>(m0 + 1);
+  int32_t* elo = cv.take<int32_t>(m0);
+  int32_t* ehi = cv.take<int32_t>(m0);
+  uint32_t* ewb = cv.take<uint32_t>(m0);
+  uint8_t* in_tree = cv.take<uint8_t>(m0);
+  int32_t* comp = cv.take<int32_t>(n);
+  int32_t* P = cv.take<int32_t>(n);
+  unsigned long long* best = cv.take<unsigned long long>(n);
+  int* hooked = cv.take<int>(1);
+  size_t tmpb = std::max(sort_pairs_u64_u32_bytes(m0), scan_i64_bytes(m0 + 1));
+  tmpb = std::max(tmpb, sort_keys_u64_bytes(m0));
+  void* tmp = cv.take<char>(tmpb);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!tu || !tv || !tw || !W) return FAMST_EINVAL;
+  if (k > 0 && (!nbr || !dist)) return FAMST_EINVAL;
+  if (n_edges > 0 && (!eu || !ev || !ew)) return FAMST_EINVAL;
+  if (m0 >= (int64_t(1) << 32)) return FAMST_ENOTIMPL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+  FAMST_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
+  FAMST_TRY(launch("mst_keys", mst_keys_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, nbr, dist, n, k,
+                   eu, ev, ew, n_edges, offs_d, B, keys, vals, bad));
+  FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, keys, skeys, vals, svals, m0, 64, s));
+  FAMST_TRY(launch("edge_unique", edge_unique_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, skeys, m0,
+                   flag));
+  FAMST_HIP(hipMemsetAsync(flag + m0, 0, sizeof(int64_t), s));
+  FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, m0 + 1, s));
+  FAMST_TRY(launch("edge_compact", edge_compact_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, skeys,
+                   svals, flag, pos, m0, elo, ehi, ewb));
+  int64_t m = 0;
+  int hbad = 0;
+  FAMST_HIP(hipMemcpyAsync(&m, pos + m0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipStreamSynchronize(s));
+  if (hbad) return FAMST_EINVAL;
+  FAMST_HIP(hipMemsetAsync(in_tree, 0, m, s));
+  if (algo == FAMST_BORUVKA) {
+    FAMST_TRY(iota_i32(comp, n, s));
+    for (int round = 0; round < 64; ++round) {
+      FAMST_TRY(fill_u64(reinterpret_cast<uint64_t*>(best), KEY_NONE, n, s));
+      FAMST_HIP(hipMemsetAsync(hooked, 0, sizeof(int), s));
+      FAMST_TRY(launch("boruvka_min", bv_min_edge_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, elo,
+                       ehi, ewb, m, comp, best));
+      FAMST_TRY(launch("boruvka_hook", bv_hook_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, elo, ehi,
+                       n, comp, best, P, in_tree, hooked));
+      FAMST_TRY(launch("boruvka_jump", bv_jump_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, comp, n,
+                       P));
+      FAMST_TRY(launch("boruvka_relabel", bv_relabel_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, comp,
+                       P, n));
+      int hh = 0;
+      FAMST_HIP(hipMemcpyAsync(&hh, hooked, sizeof(int), hipMemcpyDeviceToHost, s));
+      FAMST_HIP(hipStreamSynchronize(s));
+      if (!hh) break;
+    }
+  } else {
+    FAMST_TRY(launch("kruskal_keys", kr_keys_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, ewb, m,
+                     keys));
+    FAMST_TRY(sort_keys_u64(tmp, tmpb, keys, skeys, m, 64, s));
+    FAMST_TRY(iota_i32(P, n, s));
+    FAMST_TRY(launch("kruskal_scan", kr_scan_kernel, dim3(1), dim3(64), 0, s, skeys, m, elo, ehi, P,
+                     nt, in_tree));
+  }
+  FAMST_TRY(launch("tree_flags", u8_to_i64_kernel, dim3(cdiv(m + 1, 256)), dim3(256), 0, s, in_tree, m,
+                   flag));
+  FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, m + 1, s));
+  int64_t cnt = 0;
+  FAMST_HIP(hipMemcpyAsync(&cnt, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipStreamSynchronize(s));
+  if (cnt != nt) return FAMST_EDISCONNECTED;
+  FAMST_TRY(launch("tree_compact", tree_compact_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, in_tree,
+                   pos, m, elo, ehi, ewb, tu, tv, tw));
+  FAMST_TRY(launch("tree_weight", tree_weight_kernel, dim3(B), dim3(256), 0, s, tw, offs_d, W));
+  return FAMST_OK;
+}

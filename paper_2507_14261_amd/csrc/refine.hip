@@ -1,0 +1,192 @@
+// Phase 3 of FAMST (Alg. 4): every inter-component edge (u, v) looks at the
+// neighbours of u in its own component for a closer endpoint to v, then at
+// the neighbours of v for a closer endpoint to the new u.  Rounds repeat
+// until no edge changes (Alg. 1).
+#include "famst_common.hpp"
+#include "prims.hpp"
+
+namespace famst {
+
+struct Best {
+  float s1;   // smallest s
+  int id1;    // its id (smallest id among equal s)
+  float s2;   // second smallest s (by (s, id))
+};
+
+__device__ __forceinline__ void best_push(Best& b, float s, int id) {
+  if (key_less(s, id, b.s1, b.id1)) {
+    b.s2 = b.s1;
+    b.s1 = s;
+    b.id1 = id;
+  } else if (s < b.s2) {
+    b.s2 = s;
+  }
+}
+
+__device__ __forceinline__ Best best_merge(Best a, Best b) {
+  Best r = a;
+  if (key_less(b.s1, b.id1, a.s1, a.id1)) {
+    r.s1 = b.s1;
+    r.id1 = b.id1;
+    r.s2 = fminf(a.s1, b.s2);
+  } else {
+    r.s2 = fminf(a.s2, b.s1);
+  }
+  return r;
+}
+
+// Smallest (s(x, anchor), x) over neighbours x of `row` in component `c`
+// with x != excl; evaluated by the whole wave, four 16-lane groups at a
+// time.  Near-ties with the runner-up are settled in float64.
+__device__ Best row_argmin(const float* __restrict__ X, int d, const int64_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col, const int32_t* __restrict__ comp,
+                           int row, int c, int excl, int anchor, float tau, bool* used64,
+                           double* best64) {
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  const int64_t p0 = row_ptr[row], p1 = row_ptr[row + 1];
+  const float* xa = X + (int64_t)anchor * d;
+  Best b{F_INF, 0x7FFFFFFF, F_INF};
+  for (int64_t p = p0 + grp; p < p1; p += 4) {
+    int x = col[p];
+    if (comp[x] != c || x == excl) continue;   // uniform within the group
+    float s = sq32_group(X + (int64_t)x * d, xa, d, r16);
+    best_push(b, s, x);
+  }
+  // combine the four groups (lanes 0, 16, 32, 48 hold identical copies per group)
+#pragma unroll
+  for (int o = 16; o <= 32; o <<= 1) {
+    Best other;
+    other.s1 = __shfl_xor(b.s1, o);
+    other.id1 = __shfl_xor(b.id1, o);
+    other.s2 = __shfl_xor(b.s2, o);
+    b = best_merge(b, other);
+  }
+  *used64 = false;
+  const float up = 1.0f + 2.0f * tau, dn = 1.0f - 2.0f * tau;
+  if (b.s1 < F_INF && b.s2 * dn <= b.s1 * up) {
+    // float32 cannot order the winner against some other candidate
+    *used64 = true;
+    double m64 = __builtin_inf();
+    int mid = 0x7FFFFFFF;
+    for (int64_t p = p0 + grp; p < p1; p += 4) {
+      int x = col[p];
+      if (comp[x] != c || x == excl) continue;
+      float s = sq32_group(X + (int64_t)x * d, xa, d, r16);
+      if (s * dn <= b.s1 * up) {
+        double v = sq64_group(X + (int64_t)x * d, xa, d, r16);
+        if (key_less64(v, x, m64, mid)) {
+          m64 = v;
+          mid = x;
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      double ov = __shfl_xor(m64, o);
+      int oi = __shfl_xor(mid, o);
+      if (key_less64(ov, oi, m64, mid)) {
+        m64 = ov;
+        mid = oi;
+      }
+    }
+    // the winner's float32 value (all groups agree on mid)
+    b.id1 = mid;
+    b.s1 = sq32_group(X + (int64_t)mid * d, xa, d, r16);
+    *best64 = m64;
+  }
+  return b;
+}
+
+// strict "cand < incumbent" with float64 when float32 cannot decide
+__device__ bool strictly_less(float sc, float si, const float* ca, const float* cb, const float* ia,
+                              const float* ib, int d, float tau, bool have_c64, double c64) {
+  const float up = 1.0f + 2.0f * tau, dn = 1.0f - 2.0f * tau;
+  if (sc * up < si * dn) return true;
+  if (sc * dn > si * up) return false;
+  const int r16 = threadIdx.x & 15;
+  double vc = have_c64 ? c64 : sq64_group(ca, cb, d, r16);
+  double vi = sq64_group(ia, ib, d, r16);
+  return vc < vi;
+}
+
+__global__ __launch_bounds__(64) void refine_kernel(const float* __restrict__ X, int d,
+                                                    const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ comp,
+                                                    int32_t* __restrict__ eu, int32_t* __restrict__ ev,
+                                                    float* __restrict__ ew,
+                                                    const int32_t* __restrict__ ea,
+                                                    const int32_t* __restrict__ eb, int64_t ne,
+                                                    unsigned long long* __restrict__ delta) {
+  const int64_t e = blockIdx.x;
+  if (e >= ne) return;
+  const int r16 = threadIdx.x & 15;
+  const float tau = tau32(d);
+  const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
+  const float* xu = X + (int64_t)u * d;
+  const float* xv = X + (int64_t)v * d;
+  float ds = sq32_group(xu, xv, d, r16);
+  int us = u, vs = v;
+  // u side: neighbours of u in C_a, measured to v
+  bool u64;
+  double b64 = 0.0;
+  Best bu = row_argmin(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64);
+  if (bu.s1 < F_INF &&
+      strictly_less(bu.s1, ds, X + (int64_t)bu.id1 * d, xv, xu, xv, d, tau, u64, b64)) {
+    us = bu.id1;
+    ds = bu.s1;
+  }
+  // v side: neighbours of v in C_b (excluding the original u), measured to u*
+  const float* xus = X + (int64_t)us * d;
+  Best bv = row_argmin(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64);
+  if (bv.s1 < F_INF &&
+      strictly_less(bv.s1, ds, xus, X + (int64_t)bv.id1 * d, xus, X + (int64_t)vs * d, d, tau, u64,
+                    b64)) {
+    vs = bv.id1;
+    ds = bv.s1;
+  }
+  if (threadIdx.x == 0 && (us != u || vs != v)) {
+    eu[e] = us;
+    ev[e] = vs;
+    ew[e] = __builtin_sqrtf(ds);
+    atomicAdd(delta, 1ull);
+  }
+}
+
+}  // namespace famst
+
+using namespace famst;
+
+extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t* row_ptr,
+                            const int32_t* col, const int32_t* comp, int32_t* eu, int32_t* ev,
+                            float* ew, const int32_t* ea, const int32_t* eb, int64_t n_edges,
+                            int32_t max_rounds, int32_t* rounds_run, int64_t* deltas, void* ws,
+                            size_t* ws_bytes, void* stream) {
+  if (!ws_bytes) return FAMST_EINVAL;
+  if (n < 2 || d < 1 || n_edges < 0 || max_rounds < 1) return FAMST_EINVAL;
+  if (n_edges >= (int64_t(1) << 31)) return FAMST_ENOTIMPL;
+  Carve cv(ws);
+  unsigned long long* dc = cv.take<unsigned long long>(1);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!rounds_run || (n_edges > 0 && (!X || !row_ptr || !col || !comp || !eu || !ev || !ew || !ea || !eb)))
+    return FAMST_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int r = 0;
+  unsigned long long last = 0;
+  while (r < max_rounds) {
+    FAMST_HIP(hipMemsetAsync(dc, 0, sizeof(unsigned long long), s));
+    FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(64), 0, s, X, d, row_ptr,
+                     col, comp, eu, ev, ew, ea, eb, n_edges, dc));
+    FAMST_HIP(hipMemcpyAsync(&last, dc, sizeof(last), hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipStreamSynchronize(s));
+    if (deltas) deltas[r] = (int64_t)last;
+    ++r;
+    if (last == 0) break;
+  }
+  *rounds_run = r;
+  return last == 0 ? FAMST_OK : FAMST_WNOTCONVERGED;
+}

@@ -1,0 +1,81 @@
+"""The C-ABI library loads on a host without a GPU and exports every entry
+point the header declares (no compute calls here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "famst.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(famst_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _lib():
+    from paper_2507_14261_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libfamst.so not built")
+    return L
+
+
+def test_header_declares_the_five_phase_calls():
+    names = _declared()
+    for n in ["famst_knn_graph", "famst_connect", "famst_refine", "famst_mst", "famst_mst_backward"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(L.EXPORTS) == _declared()
+
+
+def test_exports_are_c_symbols():
+    L = _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in _declared():
+        assert name in syms, name
+
+
+def test_host_only_calls():
+    L = _lib()
+    lib = L.load()
+    assert lib.famst_version() >= 100
+    assert lib.famst_strerror(-3) == b"edges do not span every cloud"
+    assert lib.famst_strerror(0) == b"ok"
+
+
+def test_constants_match_header():
+    L = _lib()
+    txt = open(HEADER).read()
+    for name in ["FAMST_OK", "FAMST_EINVAL", "FAMST_ECAPACITY", "FAMST_EDISCONNECTED", "FAMST_EHIP",
+                 "FAMST_ENOTIMPL", "FAMST_ENONFINITE", "FAMST_EWORKSPACE", "FAMST_WNOTCONVERGED",
+                 "FAMST_FP32", "FAMST_BF16", "FAMST_FP8_E4M3", "FAMST_EXACT", "FAMST_BORUVKA",
+                 "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS"]:
+        m = re.search(r"#define\s+" + name + r"\s+\(?(-?\w+)\)?", txt)
+        assert m, name
+        assert int(m.group(1), 0) == getattr(L, name), name
+
+
+def test_invalid_arguments_rejected_before_any_launch():
+    # argument checks run on the host and never touch the device
+    L = _lib()
+    lib = L.load()
+    sz = ctypes.c_size_t(0)
+    assert lib.famst_knn_graph(None, 1, 4, None, 1, 1, 0, 0, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    assert lib.famst_knn_graph(None, 100, 4, None, 1, 100, 0, 0, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    assert lib.famst_knn_graph(None, 100, 4, None, 1, 5, 7, 0, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    assert lib.famst_knn_graph(None, 100, 4, None, 1, 5, 0, 48, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    assert lib.famst_refine(None, 100, 4, None, None, None, None, None, None, None, None, 0, 0, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    assert lib.famst_mst(None, 100, 4, None, 1, None, None, 0, None, None, None, 0, 9, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    offs = (ctypes.c_int64 * 3)(0, 1, 100)   # a one-point cloud
+    assert lib.famst_mst_backward(None, 100, 4, offs, 2, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL

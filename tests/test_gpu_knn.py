@@ -1,0 +1,103 @@
+"""Phase 1 parity: famst_knn_graph against the oracle's exact kNN."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_2507_14261_amd as F
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _run(X, k, **kw):
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(DEV)
+    out = F.knn_graph(Xd, k, with_stats=True, **kw)
+    torch.cuda.synchronize()
+    return out[0].cpu().numpy(), out[1].cpu().numpy(), out[2]
+
+
+def _check_exact(X, k, nbr, dist, rtol=1e-5):
+    ref_n, ref_s = oracle.knn_exact(X, k)
+    for i in range(len(X)):
+        assert set(nbr[i].tolist()) == set(ref_n[i].tolist()), (i, nbr[i], ref_n[i])
+    # distances: the GPU lists are sorted by the float32 value; compare sorted
+    np.testing.assert_allclose(np.sort(dist, axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=rtol, atol=1e-6)
+    assert np.all(np.diff(dist, axis=1) >= 0)
+
+
+@pytest.mark.parametrize("n,d,k", [(1000, 32, 10), (777, 17, 5), (2100, 3, 1), (513, 100, 20),
+                                   (300, 128, 24), (97, 8, 40)])
+def test_knn_fp32_exact_matches_oracle(n, d, k):
+    print(f"case n={n} d={d} k={k}", flush=True)
+    X = datagen.blobs(n=n, d=d, n_clusters=5, seed=n)
+    nbr, dist, st = _run(X, k, precision="fp32", exact=True)
+    _check_exact(X, k, nbr, dist)
+
+
+def test_knn_blobs_paper_workload_subsample():
+    X = datagen.blobs(n=4000, d=32, n_clusters=10, seed=0)
+    nbr, dist, st = _run(X, 10, precision="fp32", exact=True)
+    _check_exact(X, 10, nbr, dist)
+    print("stats", st)
+
+
+def test_knn_integer_data_bf16_equals_fp32_bitwise():
+    X = datagen.gamma_int(n=3000, d=128, n_clusters=20, seed=1)
+    a = _run(X, 20, precision="fp32", exact=True)
+    b = _run(X, 20, precision="bf16", exact=True)
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+    _check_exact(X, 20, a[0], a[1])
+    # integer data: every squared distance is an exact float32 integer
+    ref_n, ref_s = oracle.knn_exact(X, 20)
+    np.testing.assert_array_equal(np.sort(a[1] ** 2, axis=1).round(), np.sort(ref_s, axis=1))
+
+
+def test_knn_bf16_screen_recall_and_exact_flag():
+    X = datagen.blobs(n=2000, d=64, n_clusters=8, seed=4)
+    ref_n, _ = oracle.knn_exact(X, 10)
+    nbr, dist, st = _run(X, 10, precision="bf16", exact=False)
+    rec = oracle.recall_at_k(nbr, ref_n)
+    print("bf16 recall", rec, st)
+    assert rec >= 0.99
+    nbr2, dist2, st2 = _run(X, 10, precision="bf16", exact=True)
+    _check_exact(X, 10, nbr2, dist2)
+
+
+def test_knn_duplicates_and_ties():
+    rng = np.random.default_rng(0)
+    base = rng.integers(0, 3, size=(300, 4)).astype(np.float32)
+    X = np.concatenate([base, base[:50]])
+    nbr, dist, st = _run(X, 8, precision="fp32", exact=True)
+    ref_n, ref_s = oracle.knn_exact(X, 8)
+    # heavy exact ties: (s, j) order is unique, so the lists must be identical
+    assert np.array_equal(nbr, ref_n)
+    np.testing.assert_allclose(dist, np.sqrt(ref_s), rtol=1e-7)
+
+
+def test_knn_batched_clouds():
+    X, offs = datagen.clouds(n_clouds=5, lo=40, hi=700, d=24, seed=2)
+    nbr, dist, st = _run(X, 7, precision="fp32", exact=True, offs=offs)
+    for b in range(5):
+        sl = slice(offs[b], offs[b + 1])
+        ref_n, ref_s = oracle.knn_exact(X[sl], 7)
+        got = nbr[sl] - offs[b]
+        assert np.all(got >= 0) and np.all(got < offs[b + 1] - offs[b])
+        for i in range(len(ref_n)):
+            assert set(got[i].tolist()) == set(ref_n[i].tolist())
+
+
+def test_knn_k_is_n_minus_1():
+    X = datagen.blobs(n=41, d=6, n_clusters=2, seed=1)
+    nbr, dist, st = _run(X, 40, precision="fp32", exact=True)
+    for i in range(41):
+        assert sorted(nbr[i].tolist()) == [j for j in range(41) if j != i]
+
+
+def test_knn_deterministic():
+    X = datagen.blobs(n=1500, d=32, n_clusters=4, seed=9)
+    a = _run(X, 10, precision="fp32", exact=True)
+    b = _run(X, 10, precision="fp32", exact=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

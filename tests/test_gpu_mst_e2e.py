@@ -1,0 +1,164 @@
+"""Phase 4, whole-pipeline and gradient parity on the GPU."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_2507_14261_amd as F
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _graph(n, m, seed, int_w):
+    rng = np.random.default_rng(seed)
+    eu = np.concatenate([np.arange(1, n), rng.integers(0, n, size=m)])
+    ev = np.concatenate([[rng.integers(0, i) for i in range(1, n)], rng.integers(0, n, size=m)])
+    if int_w:
+        w = rng.integers(1, 6, size=len(eu)).astype(np.float32)
+    else:
+        w = rng.uniform(0.1, 10, size=len(eu)).astype(np.float32)
+    return eu.astype(np.int32), ev.astype(np.int32), w
+
+
+def _gpu_tree(n, eu, ev, w, algo, offs=None):
+    X = torch.zeros((n, 1), device=DEV)
+    E = F.Edges(_dev(eu, torch.int32), _dev(ev, torch.int32), _dev(w, torch.float32),
+                torch.zeros(len(eu), dtype=torch.int32, device=DEV), torch.zeros(len(eu), dtype=torch.int32, device=DEV))
+    tu, tv, tw, W = F.mst(X, None, None, E, algo=algo, offs=offs)
+    return tu.cpu().numpy(), tv.cpu().numpy(), tw.cpu().numpy(), W.cpu().numpy()
+
+
+@pytest.mark.parametrize("algo", ["boruvka", "kruskal"])
+@pytest.mark.parametrize("seed,int_w", [(0, False), (1, True), (2, True), (3, False)])
+def test_tree_on_given_edge_list_bit_exact(algo, seed, int_w):
+    n = 2000
+    eu, ev, w = _graph(n, 6000, seed, int_w)
+    # duplicates of existing edges with the same weight
+    eu = np.concatenate([eu, eu[:100]])
+    ev = np.concatenate([ev, ev[:100]])
+    w = np.concatenate([w, w[:100]])
+    tu, tv, tw, W = _gpu_tree(n, eu, ev, w, algo)
+    ru, rv, rw, RW, sp = oracle.kruskal(n, eu, ev, w.astype(np.float64))
+    assert sp
+    got = sorted(zip(tu.tolist(), tv.tolist(), tw.tolist()))
+    ref = sorted(zip(ru.tolist(), rv.tolist(), rw.tolist()))
+    assert got == ref
+    assert np.all(tu < tv)
+    assert np.all(np.diff(tu.astype(np.int64) * n + tv) > 0)      # ascending (min, max)
+    assert math.isclose(float(W[0]), RW, rel_tol=2e-7)
+
+
+def test_boruvka_equals_kruskal_and_disconnected_reported():
+    n = 500
+    eu, ev, w = _graph(n, 1500, 9, True)
+    a = _gpu_tree(n, eu, ev, w, "boruvka")
+    b = _gpu_tree(n, eu, ev, w, "kruskal")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    keep = (eu != 7) & (ev != 7)
+    with pytest.raises(F.FamstError) as ei:
+        _gpu_tree(n, eu[keep], ev[keep], w[keep], "boruvka")
+    assert ei.value.code == -3
+
+
+def test_tree_batched_clouds():
+    offs = np.array([0, 300, 301 + 300, 1000])
+    parts = []
+    for b in range(3):
+        nb = offs[b + 1] - offs[b]
+        eu, ev, w = _graph(int(nb), 900, 20 + b, True)
+        parts.append((eu + offs[b], ev + offs[b], w))
+    eu = np.concatenate([p[0] for p in parts]).astype(np.int32)
+    ev = np.concatenate([p[1] for p in parts]).astype(np.int32)
+    w = np.concatenate([p[2] for p in parts])
+    tu, tv, tw, W = _gpu_tree(1000, eu, ev, w, "boruvka", offs=offs)
+    for b in range(3):
+        ru, rv, rw, RW, sp = oracle.kruskal(1000, *[p for p in parts[b][:2]], parts[b][2].astype(np.float64))
+        assert math.isclose(float(W[b]), RW, rel_tol=2e-7)
+
+
+@pytest.mark.parametrize("n,d", [(300, 8), (1200, 64), (64, 3)])
+def test_dense_prim_is_exact_mst(n, d):
+    X = datagen.blobs(n=n, d=d, n_clusters=4, seed=n)
+    tu, tv, tw, W = F.mst(_dev(X, torch.float32), algo="prim")
+    ref = oracle.prim_exact(X)
+    assert math.isclose(float(W[0].item()), ref[3], rel_tol=1e-5)
+    # same tree as Boruvka on the complete kNN graph (k = n - 1)
+    if n <= 300:
+        Xd = _dev(X, torch.float32)
+        nbr, dist = F.knn_graph(Xd, min(n - 1, 64), exact=True)
+        if n - 1 <= 64:
+            b = F.mst(Xd, nbr, dist)
+            assert torch.equal(b[0], tu) and torch.equal(b[1], tv) and torch.equal(b[2], tw)
+
+
+@pytest.mark.parametrize("n,k,lam,seed", [(10_000, 10, 5, 0), (3000, 2, 5, 1), (2000, 5, 3, 2)])
+def test_famst_end_to_end_fp32(n, k, lam, seed):
+    print(f"case n={n} k={k} lam={lam}", flush=True)
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=seed)
+    ref = oracle.famst(X, k, lam, seed=seed)
+    out = F.famst(_dev(X, torch.float32), k, lam, seed=seed, precision="fp32")
+    W = float(out.W[0].item())
+    print("t", len(ref.comps), "W", W, ref.W, "rounds", out.rounds, ref.rounds)
+    assert abs(W - ref.W) / ref.W <= 1e-5
+    assert out.deltas == ref.deltas
+    tu, tv = out.tu.cpu().numpy(), out.tv.cpu().numpy()
+    assert len(tu) == n - 1
+    ds = oracle.DisjointSet(n)
+    assert all(ds.union(int(a), int(b)) for a, b in zip(tu, tv))
+
+
+def test_famst_bf16_rerank_error_bound():
+    X = datagen.blobs(n=6000, d=32, n_clusters=10, seed=0)
+    ref = oracle.famst(X, 10, 5, seed=0)
+    out = F.famst(_dev(X, torch.float32), 10, 5, seed=0, precision="bf16", exact=False)
+    W = float(out.W[0].item())
+    assert abs(W - ref.W) / ref.W <= 1e-3
+
+
+def test_gradient_matches_oracle_and_finite_differences():
+    # four clouds of 64 points, exact tree (k = n - 1): dense Prim
+    X, offs = datagen.clouds(n_clouds=4, sizes=[64, 64, 64, 64], d=64, seed=1)
+    Xd = _dev(X, torch.float32).requires_grad_(True)
+    W = F.MSTWeight.apply(Xd, 63, 5, 0, 10, "fp32", offs, True)
+    W.sum().backward()
+    g = Xd.grad.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for b in range(4):
+        Xb = X[offs[b]:offs[b + 1]]
+        tu, tv, _, Wb = oracle.prim_exact(Xb)
+        assert math.isclose(float(W[b].item()), Wb, rel_tol=1e-5)
+        gref = oracle.mst_weight_grad(Xb, tu, tv)
+        np.testing.assert_allclose(g[offs[b]:offs[b + 1]], gref, atol=1e-4)
+        coords = [(int(rng.integers(0, 64)), int(rng.integers(0, 64))) for _ in range(24)]
+        fd = oracle.fd_grad(lambda Y: oracle.prim_exact(Y)[3], Xb, coords, h=1e-6)
+        np.testing.assert_allclose([g[offs[b] + i, j] for i, j in coords], fd, atol=1e-4)
+
+
+def test_gradient_famst_path_scaled_by_upstream():
+    X = datagen.blobs(n=800, d=16, n_clusters=5, seed=3)
+    Xd = _dev(X, torch.float32).requires_grad_(True)
+    W = F.MSTWeight.apply(Xd, 8, 3, 0)
+    (2.5 * W.sum()).backward()
+    out = F.famst(_dev(X, torch.float32), 8, 3, seed=0)
+    gref = oracle.mst_weight_grad(X, out.tu.cpu().numpy(), out.tv.cpu().numpy())
+    np.testing.assert_allclose(Xd.grad.cpu().numpy(), 2.5 * gref, atol=1e-4)
+
+
+def test_errors():
+    X = torch.randn(100, 4, device=DEV)
+    with pytest.raises(F.FamstError):
+        F.knn_graph(X, 0)
+    Xn = X.clone()
+    Xn[5, 1] = float("nan")
+    with pytest.raises(F.FamstError) as ei:
+        F.knn_graph(Xn, 3)
+    assert ei.value.code == -6

@@ -1,0 +1,137 @@
+"""Phase 2 and Phase 3 parity: famst_connect (Alg. 2, Alg. 3) and
+famst_refine (Alg. 4) against the oracle on the same neighbour lists."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_2507_14261_amd as F
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _connect(X, nbr, lam, seed, offs=None):
+    G, E = F.connect(_dev(X, torch.float32), _dev(nbr, torch.int32), lam, seed, offs=offs)
+    torch.cuda.synchronize()
+    return G, E
+
+
+def _edges_np(E):
+    return tuple(t.cpu().numpy() for t in (E.u, E.v, E.w, E.a, E.b))
+
+
+@pytest.mark.parametrize("k,n", [(1, 3000), (2, 3000), (10, 4000), (3, 1537)])
+def test_graph_and_components_bit_exact(k, n):
+    print(f"case k={k} n={n}", flush=True)
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=0)
+    nbr, sq = oracle.knn_exact(X, k)
+    G, E = _connect(X, nbr, 3, 0)
+    Gref = oracle.undirected_graph(nbr)
+    comp_ref, comps_ref = oracle.components(Gref)
+    row_ptr = G.row_ptr.cpu().numpy()
+    col = G.col.cpu().numpy()
+    assert row_ptr[-1] == len(col) == sum(len(g) for g in Gref)
+    for i in range(n):
+        assert np.array_equal(col[row_ptr[i]:row_ptr[i + 1]], Gref[i])
+    assert np.array_equal(G.comp.cpu().numpy(), comp_ref)
+    assert G.n_comp == [len(comps_ref)]
+    members = G.members.cpu().numpy()
+    comp_ptr = G.comp_ptr.cpu().numpy()
+    for c, m in enumerate(comps_ref):
+        assert np.array_equal(members[comp_ptr[c]:comp_ptr[c + 1]], m)
+
+
+def _pair_sets(u, v, a, b):
+    out = {}
+    for uu, vv, aa, bb in zip(u.tolist(), v.tolist(), a.tolist(), b.tolist()):
+        out.setdefault((aa, bb), []).append((uu, vv))
+    return {key: sorted(val) for key, val in out.items()}
+
+
+@pytest.mark.parametrize("k,lam,seed,n", [(2, 5, 0, 2500), (1, 3, 7, 600), (10, 5, 0, 2500),
+                                          (3, 10, 123456789012, 2500)])
+def test_lambda_edges_match_oracle(k, lam, seed, n):
+    print(f"case k={k} lam={lam} seed={seed} n={n}", flush=True)
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=1)
+    nbr, sq = oracle.knn_exact(X, k)
+    G, E = _connect(X, nbr, lam, seed)
+    Gref = oracle.undirected_graph(nbr)
+    comp_ref, comps_ref = oracle.components(Gref)
+    t = len(comps_ref)
+    if t > 200:
+        pytest.skip("oracle sampling too slow for this t")
+    Eref = oracle.random_edges(X, comps_ref, lam, seed)
+    u, v, w, a, b = _edges_np(E)
+    assert len(u) == len(Eref) == lam * t * (t - 1) // 2
+    # entry order: pairs in (a, b) order, lambda entries each
+    assert np.array_equal(a, Eref.a) and np.array_equal(b, Eref.b)
+    assert _pair_sets(u, v, a, b) == _pair_sets(Eref.u, Eref.v, Eref.a, Eref.b)
+    np.testing.assert_allclose(np.sort(w), np.sort(np.sqrt(Eref.s)), rtol=1e-5)
+
+
+def test_lambda_edges_batched_use_cloud_counter():
+    X, offs = datagen.clouds(n_clouds=3, lo=200, hi=400, d=16, seed=5)
+    k, lam, seed = 2, 3, 9
+    nbr = np.concatenate([oracle.knn_exact(X[offs[b]:offs[b + 1]], k)[0] + offs[b] for b in range(3)])
+    G, E = _connect(X, nbr, lam, seed, offs=offs)
+    u, v, w, a, b = _edges_np(E)
+    comp = G.comp.cpu().numpy()
+    base = 0
+    got = _pair_sets(u, v, a, b)
+    for cb in range(3):
+        Xb = X[offs[cb]:offs[cb + 1]]
+        nb_local = nbr[offs[cb]:offs[cb + 1]] - offs[cb]
+        comp_ref, comps_ref = oracle.components(oracle.undirected_graph(nb_local))
+        assert G.n_comp[cb] == len(comps_ref)
+        np.testing.assert_array_equal(comp[offs[cb]:offs[cb + 1]], comp_ref + base)
+        Eref = oracle.random_edges(Xb, comps_ref, lam, seed, cloud=cb)
+        ref = _pair_sets(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base, Eref.b + base)
+        for key, val in ref.items():
+            assert got[key] == val
+        base += len(comps_ref)
+
+
+def _edges_to_oracle(u, v, w, a, b):
+    return oracle.EdgeSet(u.astype(np.int64), v.astype(np.int64), (w.astype(np.float64)) ** 2,
+                          a.astype(np.int64), b.astype(np.int64))
+
+
+@pytest.mark.parametrize("k,lam,n", [(2, 5, 3000), (1, 2, 500), (10, 5, 3000)])
+def test_refine_rounds_match_oracle(k, lam, n):
+    print(f"case k={k} lam={lam} n={n}", flush=True)
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=2)
+    nbr, sq = oracle.knn_exact(X, k)
+    G, E = _connect(X, nbr, lam, 3)
+    Gref = oracle.undirected_graph(nbr)
+    comp_ref, comps_ref = oracle.components(Gref)
+    Er = _edges_to_oracle(*_edges_np(E))
+    Er.s = np.array([oracle.sqdist(oracle.as64(X), int(p), int(q)) for p, q in zip(Er.u, Er.v)])
+    Xd = _dev(X, torch.float32)
+    for r in range(12):
+        rounds, deltas, conv = F.refine(Xd, G, E, max_rounds=1)
+        Er, dref = oracle.refine_edges(X, Gref, comp_ref, Er)
+        u, v, w, a, b = _edges_np(E)
+        assert deltas[0] == dref, (r, deltas, dref)
+        assert np.array_equal(u, Er.u) and np.array_equal(v, Er.v), r
+        np.testing.assert_allclose(w, np.sqrt(Er.s), rtol=1e-5)
+        if dref == 0:
+            break
+    assert dref == 0
+
+
+def test_refine_multi_round_call_and_not_converged_warning():
+    X = datagen.blobs(n=1500, d=32, n_clusters=10, seed=2)
+    nbr, _ = oracle.knn_exact(X, 1)
+    Xd = _dev(X, torch.float32)
+    G, E = _connect(X, nbr, 4, 1)
+    E2 = F.Edges(*(t.clone() for t in (E.u, E.v, E.w, E.a, E.b)))
+    rounds, deltas, conv = F.refine(Xd, G, E, max_rounds=1)
+    assert rounds == 1 and deltas[0] > 0 and not conv
+    rounds, deltas, conv = F.refine(Xd, G, E2, max_rounds=50)
+    assert conv and deltas[-1] == 0 and rounds == len(deltas)
