@@ -224,6 +224,24 @@ int famst_mst_backward(const float* X, int64_t n, int32_t d,
                        void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * Exact tree weight and its gradient for a batch of clouds in one
+ * persistent launch (FAMST with k = n_b - 1 is the exact minimum spanning
+ * tree, Sec. 2.1 / Prim).  Blocks take clouds from a work queue, largest
+ * first; each runs dense Prim on the complete graph of its cloud (distances
+ * computed on the fly), the compensated tree weight W[b], and the rows of
+ *   G = dW_b / dX = sum over tree edges (i, j) of (x_i - x_j)/|x_i - x_j|
+ * for that cloud.  Tree edges are written cloud by cloud in Prim insertion
+ * order as (tu, tv) = (parent, child); each row of G sums its parent edge
+ * first, then its children in ascending id, so G is deterministic.
+ *   tu, tv, tw  out [n - B];  W out [B];  grad_X out [n][d] (unscaled G)
+ * Every cloud must hold at most 12288 points (FAMST_ENOTIMPL otherwise).
+ */
+int famst_mst_dense_fused(const float* X, int64_t n, int32_t d,
+                          const int64_t* offs, int32_t B,
+                          int32_t* tu, int32_t* tv, float* tw, float* W, float* grad_X,
+                          void* ws, size_t* ws_bytes, void* stream);
+
+/*
  * Kernel timing for measurement.  While enabled, every kernel the library
  * queues is bracketed by HIP events on its stream.  famst_profile_read
  * synchronises the recorded events and returns, for kernel name `name`,

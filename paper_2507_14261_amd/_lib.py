@@ -29,7 +29,7 @@ FAMST_NSTATS = 8
 
 EXPORTS = [
     "famst_strerror", "famst_version", "famst_knn_graph", "famst_connect", "famst_refine",
-    "famst_mst", "famst_mst_backward", "famst_profile_enable", "famst_profile_reset",
+    "famst_mst", "famst_mst_backward", "famst_mst_dense_fused", "famst_profile_enable", "famst_profile_reset",
     "famst_profile_read",
 ]
 
@@ -74,6 +74,8 @@ def load():
     lib.famst_mst.argtypes = [P, I64, I32, PI64, I32, P, P, I32, P, P, P, I64, I32, P, P, P, P, P, PSZ, P]
     lib.famst_mst_backward.restype = ctypes.c_int
     lib.famst_mst_backward.argtypes = [P, I64, I32, PI64, I32, P, P, P, P, P, PSZ, P]
+    lib.famst_mst_dense_fused.restype = ctypes.c_int
+    lib.famst_mst_dense_fused.argtypes = [P, I64, I32, PI64, I32, P, P, P, P, P, P, PSZ, P]
     lib.famst_profile_enable.restype = ctypes.c_int
     lib.famst_profile_enable.argtypes = [ctypes.c_int]
     lib.famst_profile_reset.restype = ctypes.c_int

@@ -206,6 +206,25 @@ def mst_backward(X, tu, tv, gW, offs=None):
     return grad
 
 
+def mst_dense_fused(X, offs=None):
+    """Exact tree of every cloud, its weight and the gradient in one
+    persistent launch.  Returns (tu, tv, tw, W, G) with G = dW/dX."""
+    lib = L.load()
+    X = _dev(X, torch.float32, "X")
+    n, d = X.shape
+    o, B = _offs(offs, n)
+    dev = X.device
+    tu = torch.empty(n - B, dtype=torch.int32, device=dev)
+    tv = torch.empty(n - B, dtype=torch.int32, device=dev)
+    tw = torch.empty(n - B, dtype=torch.float32, device=dev)
+    W = torch.empty(B, dtype=torch.float32, device=dev)
+    G = torch.empty_like(X)
+    code, _ = _workspace(lib.famst_mst_dense_fused, _ptr(X), n, d, _offs_ptr(o), B, _ptr(tu), _ptr(tv),
+                         _ptr(tw), _ptr(W), _ptr(G))
+    L.check(code, "famst_mst_dense_fused")
+    return tu, tv, tw, W, G
+
+
 # ------------------------------------------------------------ Alg. 1
 @dataclass
 class FamstOut:
@@ -247,17 +266,27 @@ class MSTWeight(torch.autograd.Function):
     @staticmethod
     def forward(ctx, X, k, lam, seed=0, max_rounds=10, precision="fp32", offs=None, dense=False):
         Xd = X.detach().contiguous()
+        ctx.offs = offs
+        ctx.dense = dense
         if dense:
-            tu, tv, tw, W = mst(Xd, algo="prim", offs=offs)
+            # exact trees: weight and gradient come from the same persistent launch
+            tu, tv, tw, W, G = mst_dense_fused(Xd, offs=offs)
+            ctx.save_for_backward(G)
         else:
             out = famst(Xd, k, lam, seed, max_rounds, precision, offs=offs)
             tu, tv, W = out.tu, out.tv, out.W
-        ctx.save_for_backward(Xd, tu, tv)
-        ctx.offs = offs
+            ctx.save_for_backward(Xd, tu, tv)
         return W
 
     @staticmethod
     def backward(ctx, gW):
+        if ctx.dense:
+            (G,) = ctx.saved_tensors
+            n = G.shape[0]
+            o, B = _offs(ctx.offs, n)
+            sizes = torch.from_numpy(np.diff(o) if o is not None else np.array([n])).to(G.device)
+            scale = torch.repeat_interleave(gW.reshape(-1).to(G.dtype), sizes)
+            return G * scale[:, None], None, None, None, None, None, None, None
         Xd, tu, tv = ctx.saved_tensors
         grad = mst_backward(Xd, tu, tv, gW.contiguous(), offs=ctx.offs)
         return grad, None, None, None, None, None, None, None

@@ -17,42 +17,62 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
                                                    int DP, void* __restrict__ Xq,
                                                    float* __restrict__ nq, float* __restrict__ qerr,
                                                    unsigned* __restrict__ gstat) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const float* x = X + row * d;
-  float acc = 0.f, eacc = 0.f;
-  bool bad = false;
-  for (int t = lane; t < DP; t += 64) {
-    float v = t < d ? x[t] : 0.f;
-    bad |= !__builtin_isfinite(v);
-    float q;
-    if (PREC == FAMST_FP32) {
-      q = v;
-      reinterpret_cast<float*>(Xq)[row * DP + t] = q;
-    } else {
-      uint16_t b = f32_to_bf16_rne(v);
-      q = bf16_to_f32(b);
-      reinterpret_cast<uint16_t*>(Xq)[row * DP + t] = b;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned bad_any = 0, max_nq = 0, max_e = 0;   // meaningful in lane 0
+  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < n; row += (int64_t)gridDim.x * 4) {
+    const float* x = X + row * d;
+    float acc = 0.f, eacc = 0.f;
+    bool bad = false;
+    for (int t = lane; t < DP; t += 64) {
+      float v = t < d ? x[t] : 0.f;
+      bad |= !__builtin_isfinite(v);
+      float q;
+      if (PREC == FAMST_FP32) {
+        q = v;
+        reinterpret_cast<float*>(Xq)[row * DP + t] = q;
+      } else {
+        uint16_t b = f32_to_bf16_rne(v);
+        q = bf16_to_f32(b);
+        reinterpret_cast<uint16_t*>(Xq)[row * DP + t] = b;
+      }
+      acc = __builtin_fmaf(q, q, acc);
+      float e = q - v;
+      eacc = __builtin_fmaf(e, e, eacc);
     }
-    acc = __builtin_fmaf(q, q, acc);
-    float e = q - v;
-    eacc = __builtin_fmaf(e, e, eacc);
-  }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    acc += __shfl_xor(acc, o);
-    eacc += __shfl_xor(eacc, o);
+    for (int o = 32; o >= 1; o >>= 1) {
+      acc += __shfl_xor(acc, o);
+      eacc += __shfl_xor(eacc, o);
+    }
+    unsigned long long anybad = ballot(bad);
+    if (lane == 0) {
+      nq[row] = acc;
+      // sqrt rounding and the float32 sum itself: inflate slightly
+      float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
+      qerr[row] = e;
+      bad_any |= anybad ? 1u : 0u;
+      max_nq = max(max_nq, __float_as_uint(acc));
+      max_e = max(max_e, __float_as_uint(e));
+    }
   }
-  unsigned long long anybad = ballot(bad);
+  // one set of atomics per block
+  __shared__ unsigned red[3][4];
   if (lane == 0) {
-    nq[row] = acc;
-    // sqrt rounding and the float32 sum itself: inflate slightly
-    float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
-    qerr[row] = e;
-    if (anybad) atomicOr(&gstat[0], 1u);
-    atomicMax(&gstat[1], __float_as_uint(acc));
-    atomicMax(&gstat[2], __float_as_uint(e));
+    red[0][w] = bad_any;
+    red[1][w] = max_nq;
+    red[2][w] = max_e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned b = 0, m1 = 0, m2 = 0;
+    for (int i = 0; i < 4; ++i) {
+      b |= red[0][i];
+      m1 = max(m1, red[1][i]);
+      m2 = max(m2, red[2][i]);
+    }
+    if (b) atomicOr(&gstat[0], 1u);
+    atomicMax(&gstat[1], m1);
+    atomicMax(&gstat[2], m2);
   }
 }
 
@@ -61,6 +81,11 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
 // cloud's rows [c0, c1).
 struct BlockDesc {
   int q0, q1, c0, c1;
+};
+
+struct __attribute__((aligned(8))) Cand {
+  float s;
+  int j;
 };
 
 template <int PREC>
@@ -86,7 +111,7 @@ struct Scr<FAMST_BF16> {
 // LDS list sorted ascending; a tile element reaches the insertion path only
 // if s is within the list's current maximum.
 template <int PREC, int NKB, int QB, int KC>
-__global__ __launch_bounds__(256, 1) void dist_topk_kernel(
+__global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int DP, int nkb,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s) {
   using S = Scr<PREC>;
@@ -97,10 +122,15 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
   const T* Xq = reinterpret_cast<const T*>(Xq_);
 
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* ls = reinterpret_cast<float*>(smem);               // [QBLK][KC]
-  int* lj = reinterpret_cast<int*>(ls + QBLK * KC);         // [QBLK][KC]
-  char* tile = reinterpret_cast<char*>(lj + QBLK * KC);     // [BN][RS]
-  const int RS = DP * S::ESZ + 16;                          // padded row stride (bytes)
+  // per-query lists of (s, j), ascending by (s, j): [QBLK][KC]
+  Cand* lst = reinterpret_cast<Cand*>(smem);
+  char* tile = reinterpret_cast<char*>(lst + QBLK * KC);    // [BN][DP*ESZ], 16-byte chunks swizzled
+  const int RS = DP * S::ESZ;                               // row bytes
+  const int cpr = RS / 16;                                  // 16-byte chunks per row (multiple of 4)
+  // chunk c of row r lives at chunk c ^ (r & smask): the 16 rows read by one
+  // lane group then fall in distinct bank groups
+  const int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
+  const int nchunk = BN * cpr;
 
   const BlockDesc bd = desc[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -108,10 +138,7 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
   const int wq0 = bd.q0 + wave * QW;   // first query of this wave
 
   // lists start as (+inf, INT_MAX)
-  for (int e = tid; e < QBLK * KC; e += 256) {
-    ls[e] = F_INF;
-    lj[e] = 0x7FFFFFFF;
-  }
+  for (int e = tid; e < QBLK * KC; e += 256) lst[e] = Cand{F_INF, 0x7FFFFFFF};
 
   // resident query fragments
   i32x4 qf[QB][NKB];
@@ -133,22 +160,77 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
       qf[qb][kb] = v;
     }
   }
-  __syncthreads();
 
-  const int cpr = DP * S::ESZ / 16;     // 16-byte chunks per row
-  const int nchunk = BN * cpr;
+  // register prefetch of one tile: thread tid owns chunks tid + 256 i
+  i32x4 pf[NKB];
+  float pnq[4][4];   // norms of the rows this lane filters: t0 + jb*16 + 4g + r
+  auto fetch = [&](int t0) {
+    if (t0 + BN <= bd.c1) {   // full tile
+#pragma unroll
+      for (int i = 0; i < NKB; ++i) {
+        int c = tid + 256 * i;
+        i32x4 v = {0, 0, 0, 0};
+        if (i < nkb) {
+          int r = c / cpr, cc = c - r * cpr;
+          v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(Xq + (int64_t)(t0 + r) * DP) + cc * 16);
+        }
+        pf[i] = v;
+      }
+      const float* np = nq + t0 + 4 * g;
+      if ((t0 & 3) == 0) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+          f32x4 v = *reinterpret_cast<const f32x4*>(np + jb * 16);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pnq[jb][r] = v[r];
+        }
+      } else {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pnq[jb][r] = np[jb * 16 + r];
+      }
+    } else {                  // ragged last tile
+#pragma unroll
+      for (int i = 0; i < NKB; ++i) {
+        int c = tid + 256 * i;
+        i32x4 v = {0, 0, 0, 0};
+        if (c < nchunk) {
+          int r = c / cpr, cc = c - r * cpr;
+          int row = t0 + r;
+          if (row < bd.c1)
+            v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(Xq + (int64_t)row * DP) + cc * 16);
+        }
+        pf[i] = v;
+      }
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int row = t0 + jb * 16 + 4 * g + r;
+          pnq[jb][r] = row < bd.c1 ? nq[row] : F_INF;
+        }
+    }
+  };
+  fetch(bd.c0);
 
   for (int t0 = bd.c0; t0 < bd.c1; t0 += BN) {
-    // ---- stage tile rows [t0, t0+64) into LDS
-    for (int c = tid; c < nchunk; c += 256) {
-      int r = c / cpr, cc = c - r * cpr;
-      int row = t0 + r;
-      i32x4 v = {0, 0, 0, 0};
-      if (row < bd.c1)
-        v = *reinterpret_cast<const i32x4*>(reinterpret_cast<const char*>(Xq + (int64_t)row * DP) + cc * 16);
-      *reinterpret_cast<i32x4*>(tile + r * RS + cc * 16) = v;
+    // ---- publish the prefetched tile, then start fetching the next one
+#pragma unroll
+    for (int i = 0; i < NKB; ++i) {
+      if (i < nkb) {   // chunk tid + 256 i exists iff i < nkb (64 rows x 4 nkb chunks)
+        int c = tid + 256 * i;
+        int r = c / cpr, cc = c - r * cpr;
+        *reinterpret_cast<i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4)) = pf[i];
+      }
     }
+    float nqj[4][4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nqj[jb][r] = pnq[jb][r];
     __syncthreads();
+    if (t0 + BN < bd.c1) fetch(t0 + BN);
 
     // ---- matrix-core products
     f32x4 acc[QB][4];
@@ -161,8 +243,9 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
       if (kb < nkb) {
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
-          i32x4 a = *reinterpret_cast<const i32x4*>(
-              tile + (jb * 16 + i16) * RS + (kb * S::KBW + g * (S::KBW / 4)) * S::ESZ);
+          const int r = jb * 16 + i16;
+          const int cc = kb * 4 + g;
+          i32x4 a = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
 #pragma unroll
           for (int qb = 0; qb < QB; ++qb) {
             if constexpr (PREC == FAMST_FP32) {
@@ -183,14 +266,6 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
     }
 
     // ---- screening filter: lane holds rows t0 + jb*16 + 4g + r, query qb*16 + i16
-    float nqj[4][4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = t0 + jb * 16 + 4 * g + r;
-        nqj[jb][r] = row < bd.c1 ? nq[row] : F_INF;
-      }
     bool any = false;
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
@@ -202,47 +277,51 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
       any |= m <= U[qb];
     }
     if (ballot(any)) {
-      // insertion path: visit passing elements one at a time (wave-uniform)
+      // insertion path: per query block, pull passing elements one at a time
+      // (wave-uniform) and insert them into their query's sorted list
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
+        float sp[16];
+        unsigned pm = 0;
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
+        for (int e = 0; e < 16; ++e) {
+          sp[e] = __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
+          pm |= (sp[e] <= U[qb] ? 1u : 0u) << e;
+        }
+        while (true) {
+          unsigned long long lanes = ballot(pm != 0);
+          if (!lanes) break;
+          const int src = __builtin_ctzll(lanes);
+          const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
+          if (lane == src) pm &= pm - 1;
+          float v = sp[0];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float sp = __builtin_fmaf(-2.f, acc[qb][jb][r], nqj[jb][r]);
-            unsigned long long mask = ballot(sp <= U[qb]);
-            while (mask) {
-              int src = __builtin_ctzll(mask);
-              mask &= mask - 1;
-              int qi = qb * 16 + (src & 15);                    // query within wave
-              int j = t0 + jb * 16 + 4 * (src >> 4) + r;         // candidate row
-              int q = wq0 + qi;
-              float s = readlane_f(sp, src) + readlane_f(nqq[qb], src);
-              if (j >= bd.c1 || j == q) continue;
-              volatile float* L = ls + (wave * QW + qi) * KC;
-              volatile int* J = lj + (wave * QW + qi) * KC;
-              float cs = lane < KC ? L[lane] : F_INF;
-              int cj = lane < KC ? J[lane] : 0x7FFFFFFF;
-              bool lt = lane < KC && key_less(cs, cj, s, j);
-              int pos = __builtin_popcountll(ballot(lt));
-              if (pos >= KC) continue;
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-              if (lane >= pos && lane < KC - 1) {
-                L[lane + 1] = cs;
-                J[lane + 1] = cj;
-              }
-              if (lane == pos) {
-                L[lane] = s;
-                J[lane] = j;
-              }
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-              float Tn = (pos == KC - 1) ? s : readlane_f(cs, KC - 2);
-              // a few ulps of slack so rounding in U never hides an equal key
-              float Un = Tn - nqq[qb];
-              Un = Un + fabsf(Tn) * 2.4e-7f;
-              if (i16 == (src & 15)) U[qb] = Un;
-            }
-          }
+          for (int x = 1; x < 16; ++x) v = (e == x) ? sp[x] : v;
+          const float spv = readlane_f(v, src);
+          if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
+          const int qi = qb * 16 + (src & 15);                 // query within wave
+          const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
+          const int q = wq0 + qi;
+          if (j >= bd.c1 || j == q) continue;
+          const float s = spv + readlane_f(nqq[qb], src);
+          Cand* L = lst + (wave * QW + qi) * KC;
+          Cand c = lane < KC ? L[lane] : Cand{F_INF, 0x7FFFFFFF};
+          const bool lt = lane < KC && key_less(c.s, c.j, s, j);
+          const int pos = __builtin_popcountll(ballot(lt));
+          if (pos >= KC) continue;
+          // shift the tail up by one: lane l takes lane l-1's entry (DPP
+          // wave_shr:1)
+          const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(c.s), 0x138, 0xF, 0xF, false));
+          const int upj = __builtin_amdgcn_update_dpp(0, c.j, 0x138, 0xF, 0xF, false);
+          Cand nc;
+          nc.s = lane < pos ? c.s : (lane == pos ? s : ups);
+          nc.j = lane < pos ? c.j : (lane == pos ? j : upj);
+          if (lane < KC) L[lane] = nc;
+          const float Tn = readlane_f(nc.s, KC - 1);
+          // a few ulps of slack so rounding in U never hides an equal key
+          float Un = Tn - nqq[qb];
+          Un = Un + fabsf(Tn) * 2.4e-7f;
+          if (i16 == (src & 15)) U[qb] = Un;
         }
       }
     }
@@ -256,8 +335,9 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
       int qi = qb * 16 + qq;
       int q = wq0 + qi;
       if (q < bd.q1 && lane < KC) {
-        cand_s[(int64_t)q * KC + lane] = ls[(wave * QW + qi) * KC + lane];
-        cand_j[(int64_t)q * KC + lane] = lj[(wave * QW + qi) * KC + lane];
+        Cand c = lst[(wave * QW + qi) * KC + lane];
+        cand_s[(int64_t)q * KC + lane] = c.s;
+        cand_j[(int64_t)q * KC + lane] = c.j;
       }
     }
   }
@@ -410,7 +490,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.QB = (p.KC == 64) ? 2 : 4;
   p.qblk = 64 * p.QB;
   const int esz = prec == FAMST_FP32 ? 4 : 2;
-  p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * (p.DP * esz + 16);
+  p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * esz;
   if (p.lds > 160 * 1024) return FAMST_ENOTIMPL;
   return FAMST_OK;
 }
@@ -512,10 +592,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (e1 || e2 || e3 || e4 || e5 || e6) return FAMST_EHIP;
 
   if (prec == FAMST_FP32)
-    FAMST_TRY(launch("prep", prep_kernel<FAMST_FP32>, dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, d,
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_FP32>, dim3(std::min<unsigned>(cdiv(n, 4), 4096)), dim3(256), 0, s, X, n, d,
                      p.DP, Xq, nq, qerr, gstat));
   else
-    FAMST_TRY(launch("prep", prep_kernel<FAMST_BF16>, dim3(cdiv(n, 4)), dim3(256), 0, s, X, n, d,
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_BF16>, dim3(std::min<unsigned>(cdiv(n, 4), 4096)), dim3(256), 0, s, X, n, d,
                      p.DP, Xq, nq, qerr, gstat));
   unsigned bad_flag = 0;
   FAMST_HIP(hipMemcpyAsync(&bad_flag, gstat, 4, hipMemcpyDeviceToHost, s));

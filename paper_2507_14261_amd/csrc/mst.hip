@@ -3,6 +3,7 @@
 // under that strict order the minimum spanning tree is unique, so Boruvka
 // (Sec. 2.1) and Kruskal (Sec. 2.1, the paper's choice) give the same tree.
 // Also the exact tree of the complete graph by Prim (Sec. 2.1) for k = n-1.
+#include <algorithm>
 #include <vector>
 
 #include "famst_common.hpp"
@@ -297,6 +298,168 @@ __global__ __launch_bounds__(256) void prim_kernel(const float* __restrict__ X, 
   }
 }
 
+// Persistent exact-tree kernel for a batch of clouds: blocks pull clouds
+// from an atomic queue (largest first) and, for each, run dense Prim, the
+// compensated tree weight and the gradient rows of the cloud, all in one
+// launch.  Tree edges are written in Prim insertion order as (parent,
+// child).  The gradient of row v sums its parent edge first, then its
+// children in ascending order, so it is deterministic.
+constexpr int FUSED_MAX = 12288;
+
+__global__ __launch_bounds__(256) void prim_fused_kernel(
+    const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
+    int B, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
+    float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float* bw = reinterpret_cast<float*>(smem);             // best weight to the tree; -1 once in the tree
+  int* par = reinterpret_cast<int*>(bw + FUSED_MAX);      // tree endpoint of that best edge (parent)
+  int* kid = par + FUSED_MAX;                             // children lists (after the tree is built)
+  __shared__ float rw[256];
+  __shared__ int rj[256];
+  __shared__ int cur_s, cloud_s;
+  __shared__ float ss[256], ee[256];
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  while (true) {
+    if (t == 0) {
+      int idx = atomicAdd(queue, 1);
+      cloud_s = idx < B ? order[idx] : -1;
+    }
+    __syncthreads();
+    const int b = cloud_s;
+    if (b < 0) break;
+    const int64_t c0 = offs[b];
+    const int nb = (int)(offs[b + 1] - c0);
+    const int64_t eo = c0 - b;
+    for (int j = t; j < nb; j += 256) {
+      bw[j] = F_INF;
+      par[j] = -1;
+    }
+    __syncthreads();
+    if (t == 0) {
+      bw[0] = -1.f;
+      cur_s = 0;
+    }
+    __syncthreads();
+    // ---- dense Prim
+    for (int step = 1; step < nb; ++step) {
+      const int cur = cur_s;
+      const float* xc = X + (c0 + cur) * d;
+      for (int j = grp; j < nb; j += 16) {
+        if (bw[j] < 0.f) continue;  // in the tree (uniform in group)
+        float s = sq32_group(xc, X + (c0 + j) * d, d, r16);
+        float w = __builtin_sqrtf(s);
+        if (r16 == 0) {
+          int f = par[j];
+          if (f < 0 || ekey_less(w, cur, j, bw[j], f, j)) {
+            bw[j] = w;
+            par[j] = cur;
+          }
+        }
+      }
+      __syncthreads();
+      float mw = F_INF;
+      int mj = -1;
+      for (int j = t; j < nb; j += 256) {
+        if (bw[j] < 0.f) continue;
+        if (mj < 0 || ekey_less(bw[j], par[j], j, mw, par[mj], mj)) {
+          mw = bw[j];
+          mj = j;
+        }
+      }
+      rw[t] = mw;
+      rj[t] = mj;
+      __syncthreads();
+      for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+          int oj = rj[t + w];
+          if (oj >= 0 && (rj[t] < 0 || ekey_less(rw[t + w], par[oj], oj, rw[t], par[rj[t]], rj[t]))) {
+            rw[t] = rw[t + w];
+            rj[t] = oj;
+          }
+        }
+        __syncthreads();
+      }
+      if (t == 0) {
+        int j = rj[0];
+        ou[eo + step - 1] = (int32_t)(c0 + par[j]);
+        ov[eo + step - 1] = (int32_t)(c0 + j);
+        ow[eo + step - 1] = rw[0];
+        bw[j] = -1.f;
+        cur_s = j;
+      }
+      __syncthreads();
+    }
+    // ---- tree weight, compensated, in insertion order
+    {
+      float sacc = 0.f, cacc = 0.f;
+      for (int i = t; i < nb - 1; i += 256) {
+        float ns, err;
+        two_sum(sacc, ow[eo + i], ns, err);
+        sacc = ns;
+        cacc += err;
+      }
+      ss[t] = sacc;
+      ee[t] = cacc;
+      __syncthreads();
+      for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+          float ns, err;
+          two_sum(ss[t], ss[t + w], ns, err);
+          ss[t] = ns;
+          ee[t] = ee[t] + ee[t + w] + err;
+        }
+        __syncthreads();
+      }
+      if (t == 0) W[b] = ss[0] + ee[0];
+    }
+    // ---- children lists by counting sort, stable in child id (one thread;
+    // bw is reused for the list ends)
+    int* endp = reinterpret_cast<int*>(bw);
+    for (int j = t; j < nb; j += 256) endp[j] = 0;
+    __syncthreads();
+    if (t == 0) {
+      for (int c = 1; c < nb; ++c) endp[par[c]] += 1;
+      int run = 0;
+      for (int p = 0; p < nb; ++p) {
+        int cnt = endp[p];
+        endp[p] = run;
+        run += cnt;
+      }
+      for (int c = 1; c < nb; ++c) kid[endp[par[c]]++] = c;
+    }
+    __syncthreads();
+    // ---- gradient rows, one 16-lane group per row
+    for (int v = grp; v < nb; v += 16) {
+      const float* xv = X + (c0 + v) * d;
+      float* out = grad + (c0 + v) * d;
+      const int k0 = v == 0 ? 0 : endp[v - 1], k1 = endp[v];
+      for (int t0 = 0; t0 < d; t0 += 16 * 8) {
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+        for (int e = (v == 0 ? k0 : k0 - 1); e < k1; ++e) {
+          const int o = (e < k0) ? par[v] : kid[e];
+          const float* xo = X + (c0 + o) * d;
+          float s = sq32_group(xv, xo, d, r16);
+          if (s == 0.f) continue;
+          float w = __builtin_sqrtf(s);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            int tt = t0 + q * 16 + r16;
+            if (tt < d) acc[q] += (xv[tt] - xo[tt]) / w;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          int tt = t0 + q * 16 + r16;
+          if (tt < d) out[tt] = acc[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void pair_keys_kernel(const int32_t* __restrict__ a, const int32_t* __restrict__ b,
                                  const float* __restrict__ w, int64_t m, uint64_t* __restrict__ keys,
                                  uint32_t* __restrict__ vals) {
@@ -463,4 +626,55 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
                    pos, m, elo, ehi, ewb, tu, tv, tw));
   FAMST_TRY(launch("tree_weight", tree_weight_kernel, dim3(B), dim3(256), 0, s, tw, offs_d, W));
   return FAMST_OK;
+}
+
+extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
+                                     int32_t B, int32_t* tu, int32_t* tv, float* tw, float* W,
+                                     float* grad_X, void* ws, size_t* ws_bytes, void* stream) {
+  if (!ws_bytes) return FAMST_EINVAL;
+  if (n < 2 || d < 1 || B < 1) return FAMST_EINVAL;
+  if (n >= (int64_t(1) << 31)) return FAMST_EINVAL;
+  int64_t one[2] = {0, n};
+  const int64_t* offs = offs_h ? offs_h : one;
+  if (!offs_h && B != 1) return FAMST_EINVAL;
+  if (offs[0] != 0 || offs[B] != n) return FAMST_EINVAL;
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) {
+    int64_t nb = offs[b + 1] - offs[b];
+    if (nb < 2) return FAMST_EINVAL;
+    if (nb > FUSED_MAX) return FAMST_ENOTIMPL;
+    order[b] = b;
+  }
+  Carve cv(ws);
+  int64_t* offs_d = cv.take<int64_t>(B + 1);
+  int* order_d = cv.take<int>(B);
+  int* queue = cv.take<int>(1);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!X || !tu || !tv || !tw || !W || !grad_X) return FAMST_EINVAL;
+  // largest clouds first (longest-processing-time order), ties by index
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return offs[a + 1] - offs[a] > offs[b + 1] - offs[b];
+  });
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
+  FAMST_HIP(hipMemcpyAsync(order_d, order.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  FAMST_HIP(hipMemsetAsync(queue, 0, sizeof(int), s));
+  FAMST_HIP(hipStreamSynchronize(s));  // host order array copied before it goes out of scope
+  int dev = 0, ncu = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  static bool attr = false;
+  const size_t lds = (size_t)3 * FUSED_MAX * 4;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(prim_fused_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  const int grid = std::min(B, ncu);
+  return launch("dense_prim_fused", prim_fused_kernel, dim3(grid), dim3(256), lds, s, X, d, offs_d,
+                order_d, B, queue, tu, tv, tw, W, grad_X);
 }

@@ -143,6 +143,32 @@ def test_gradient_matches_oracle_and_finite_differences():
         np.testing.assert_allclose([g[offs[b] + i, j] for i, j in coords], fd, atol=1e-4)
 
 
+def test_dense_fused_persistent_batch_matches_oracle():
+    # uneven cloud sizes, more clouds than a single wave of blocks would need
+    X, offs = datagen.clouds(n_clouds=40, lo=20, hi=300, d=16, seed=7)
+    Xd = _dev(X, torch.float32)
+    tu, tv, tw, W, G = F.mst_dense_fused(Xd, offs=offs)
+    torch.cuda.synchronize()
+    tu, tv, tw, W, G = (t.cpu().numpy() for t in (tu, tv, tw, W, G))
+    for b in range(40):
+        sl = slice(offs[b], offs[b + 1])
+        ref = oracle.prim_exact(X[sl])
+        assert math.isclose(float(W[b]), ref[3], rel_tol=1e-5)
+        e0, e1 = offs[b] - b, offs[b + 1] - b - 1
+        # same tree as the unfused dense path (up to edge order)
+        got = sorted(zip(np.minimum(tu[e0:e1], tv[e0:e1]).tolist(), np.maximum(tu[e0:e1], tv[e0:e1]).tolist()))
+        gref = oracle.mst_weight_grad(X[sl], tu[e0:e1] - offs[b], tv[e0:e1] - offs[b])
+        np.testing.assert_allclose(G[sl], gref, atol=1e-4)
+        assert len(got) == offs[b + 1] - offs[b] - 1
+    a = F.mst(Xd, algo="prim", offs=offs)
+    ref_pairs = sorted(zip(a[0].cpu().numpy().tolist(), a[1].cpu().numpy().tolist()))
+    all_pairs = sorted(zip(np.minimum(tu, tv).tolist(), np.maximum(tu, tv).tolist()))
+    assert all_pairs == ref_pairs
+    # deterministic: a second launch gives the same bits
+    G2 = F.mst_dense_fused(Xd, offs=offs)[4].cpu().numpy()
+    assert np.array_equal(G, G2)
+
+
 def test_gradient_famst_path_scaled_by_upstream():
     X = datagen.blobs(n=800, d=16, n_clusters=5, seed=3)
     Xd = _dev(X, torch.float32).requires_grad_(True)
