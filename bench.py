@@ -28,6 +28,8 @@ HBM_GBS = 8000.0
 WORKLOADS = {
     "gamma-int-1m-d128": ("gamma_int", dict(n=1_000_000, d=128), 20, 10),
     "blobs-10k-d32": ("blobs", dict(n=10_000, d=32), 10, 5),
+    "vmf-4m-d96": ("vmf", dict(n=4_000_000, d=96), 16, 8),
+    "lowrank-500k-d960": ("lowrank", dict(n=500_000, d=960), 20, 10),
 }
 
 

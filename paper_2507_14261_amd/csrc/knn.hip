@@ -110,6 +110,64 @@ struct Scr<FAMST_BF16> {
 // Each wave keeps, for each of its queries, the KC smallest (s, j) in an
 // LDS list sorted ascending; a tile element reaches the insertion path only
 // if s is within the list's current maximum.
+// Insertion of the tile elements that pass the screening filter into the
+// per-query sorted lists of one wave (lists at wl, [QW][KC]).  Lane
+// (g, i16) holds, for query qb*16 + i16 of the wave, the 16 elements
+// e = jb*4 + r at rows t0 + jb*16 + 4g + r; spf(qb, e) returns their
+// screened value minus the query's norm.  Elements are pulled one at a time
+// (wave-uniform); the whole wave inserts each into its query's list (a
+// ballot gives the position, DPP wave_shr:1 shifts the tail).
+template <int QB, int KC, class SpFn>
+__device__ __forceinline__ void insert_candidates(Cand* wl, unsigned qbmask, float (&U)[QB],
+                                                  const float (&nqq)[QB], SpFn spf, int t0, int c1,
+                                                  int wq0, int lane, int g, int i16) {
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    if (!(qbmask & (1u << qb))) continue;
+    float sp[16];
+    unsigned pm = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      sp[e] = spf(qb, e);
+      pm |= (sp[e] <= U[qb] ? 1u : 0u) << e;
+    }
+    while (true) {
+      unsigned long long lanes = ballot(pm != 0);
+      if (!lanes) break;
+      const int src = __builtin_ctzll(lanes);
+      const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
+      if (lane == src) pm &= pm - 1;
+      float v = sp[0];
+#pragma unroll
+      for (int x = 1; x < 16; ++x) v = (e == x) ? sp[x] : v;
+      const float spv = readlane_f(v, src);
+      if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
+      const int qi = qb * 16 + (src & 15);                 // query within wave
+      const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
+      const int q = wq0 + qi;
+      if (j >= c1 || j == q) continue;
+      const float s = spv + readlane_f(nqq[qb], src);
+      Cand* L = wl + qi * KC;
+      Cand c = lane < KC ? L[lane] : Cand{F_INF, 0x7FFFFFFF};
+      const bool lt = lane < KC && key_less(c.s, c.j, s, j);
+      const int pos = __builtin_popcountll(ballot(lt));
+      if (pos >= KC) continue;
+      // shift the tail up by one: lane l takes lane l-1's entry (DPP wave_shr:1)
+      const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(c.s), 0x138, 0xF, 0xF, false));
+      const int upj = __builtin_amdgcn_update_dpp(0, c.j, 0x138, 0xF, 0xF, false);
+      Cand nc;
+      nc.s = lane < pos ? c.s : (lane == pos ? s : ups);
+      nc.j = lane < pos ? c.j : (lane == pos ? j : upj);
+      if (lane < KC) L[lane] = nc;
+      const float Tn = readlane_f(nc.s, KC - 1);
+      // a few ulps of slack so rounding in U never hides an equal key
+      float Un = Tn - nqq[qb];
+      Un = Un + fabsf(Tn) * 2.4e-7f;
+      if (i16 == (src & 15)) U[qb] = Un;
+    }
+  }
+}
+
 template <int PREC, int NKB, int QB, int KC>
 __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int DP, int nkb,
@@ -267,6 +325,7 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
 
     // ---- screening filter: lane holds rows t0 + jb*16 + 4g + r, query qb*16 + i16
     bool any = false;
+    unsigned qbmask = 0;   // query blocks with at least one passing element (wave-uniform)
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       float m = F_INF;
@@ -274,61 +333,282 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
       for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) m = fminf(m, __builtin_fmaf(-2.f, acc[qb][jb][r], nqj[jb][r]));
-      any |= m <= U[qb];
+      const bool p = m <= U[qb];
+      any |= p;
+      qbmask |= ballot(p) ? (1u << qb) : 0u;
     }
-    if (ballot(any)) {
-      // insertion path: per query block, pull passing elements one at a time
-      // (wave-uniform) and insert them into their query's sorted list
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        float sp[16];
-        unsigned pm = 0;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          sp[e] = __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
-          pm |= (sp[e] <= U[qb] ? 1u : 0u) << e;
-        }
-        while (true) {
-          unsigned long long lanes = ballot(pm != 0);
-          if (!lanes) break;
-          const int src = __builtin_ctzll(lanes);
-          const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
-          if (lane == src) pm &= pm - 1;
-          float v = sp[0];
-#pragma unroll
-          for (int x = 1; x < 16; ++x) v = (e == x) ? sp[x] : v;
-          const float spv = readlane_f(v, src);
-          if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
-          const int qi = qb * 16 + (src & 15);                 // query within wave
-          const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
-          const int q = wq0 + qi;
-          if (j >= bd.c1 || j == q) continue;
-          const float s = spv + readlane_f(nqq[qb], src);
-          Cand* L = lst + (wave * QW + qi) * KC;
-          Cand c = lane < KC ? L[lane] : Cand{F_INF, 0x7FFFFFFF};
-          const bool lt = lane < KC && key_less(c.s, c.j, s, j);
-          const int pos = __builtin_popcountll(ballot(lt));
-          if (pos >= KC) continue;
-          // shift the tail up by one: lane l takes lane l-1's entry (DPP
-          // wave_shr:1)
-          const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(c.s), 0x138, 0xF, 0xF, false));
-          const int upj = __builtin_amdgcn_update_dpp(0, c.j, 0x138, 0xF, 0xF, false);
-          Cand nc;
-          nc.s = lane < pos ? c.s : (lane == pos ? s : ups);
-          nc.j = lane < pos ? c.j : (lane == pos ? j : upj);
-          if (lane < KC) L[lane] = nc;
-          const float Tn = readlane_f(nc.s, KC - 1);
-          // a few ulps of slack so rounding in U never hides an equal key
-          float Un = Tn - nqq[qb];
-          Un = Un + fabsf(Tn) * 2.4e-7f;
-          if (i16 == (src & 15)) U[qb] = Un;
-        }
-      }
-    }
+    if (qbmask)
+      insert_candidates<QB, KC>(lst + wave * QW * KC, qbmask, U, nqq,
+                                [&](int qb, int e) {
+                                  return __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
+                                },
+                                t0, bd.c1, wq0, lane, g, i16);
     __syncthreads();
   }
 
   // ---- write the candidate lists
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    for (int qq = 0; qq < 16; ++qq) {
+      int qi = qb * 16 + qq;
+      int q = wq0 + qi;
+      if (q < bd.q1 && lane < KC) {
+        Cand c = lst[(wave * QW + qi) * KC + lane];
+        cand_s[(int64_t)q * KC + lane] = c.s;
+        cand_j[(int64_t)q * KC + lane] = c.j;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------ K-chunked screening
+// For any d and for float8: the cloud is streamed in 64-row tiles and the
+// dimension in 256-byte chunks; both the tile chunk and the block's query
+// chunk are staged in LDS (16-byte chunks XOR-swizzled by row), so no
+// operand has to stay resident in registers.  128 queries per block, 32 per
+// wave; the filter and the insertion path are those of dist_topk_kernel.
+
+// IEEE float32 -> OCP float8 e4m3 (bias 7, max 448, no infinities), round
+// to nearest even, saturating at +-448.
+__device__ __forceinline__ uint32_t f32_to_e4m3(float v) {
+  const uint32_t sign = v < 0.f ? 0x80u : 0u;
+  const float a = fabsf(v);
+  if (!(a < 448.f)) return sign | 0x7Eu;
+  int e;
+  frexpf(a, &e);
+  int E = e - 1;                     // floor(log2 a) for a > 0
+  if (a == 0.f || E < -6) E = -6;    // subnormal spacing 2^-9
+  const float step = ldexpf(1.f, E - 3);
+  const float qv = rintf(a / step) * step;
+  if (qv == 0.f) return sign;
+  int e2;
+  frexpf(qv, &e2);
+  const int E2 = e2 - 1;
+  if (E2 < -6) return sign | (uint32_t)(qv * 512.f);          // m * 2^-9
+  const uint32_t mant = (uint32_t)(qv / ldexpf(1.f, E2 - 3)) - 8u;
+  return sign | ((uint32_t)(E2 + 7) << 3) | mant;
+}
+
+__device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
+  const uint32_t ex = (b >> 3) & 15u, m = b & 7u;
+  const float mag = ex == 0 ? (float)m * 0.001953125f : ldexpf((float)(8u + m), (int)ex - 10);
+  return (b & 0x80u) ? -mag : mag;
+}
+
+// One wave per row: per-row scale a = amax / 448 (1 for an all-zero row),
+// e4m3 codes of x / a, the norm of the dequantised row and the norm of its
+// error; gstat as in prep_kernel.
+__global__ __launch_bounds__(256) void prep_fp8_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                       int DP, uint8_t* __restrict__ Xq,
+                                                       float* __restrict__ scl, float* __restrict__ nq,
+                                                       float* __restrict__ qerr,
+                                                       unsigned* __restrict__ gstat) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned bad_any = 0, max_nq = 0, max_e = 0;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < n; row += (int64_t)gridDim.x * 4) {
+    const float* x = X + row * d;
+    float amax = 0.f;
+    bool bad = false;
+    for (int t = lane; t < d; t += 64) {
+      float v = x[t];
+      bad |= !__builtin_isfinite(v);
+      amax = fmaxf(amax, fabsf(v));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+    const float a = amax > 0.f ? amax / 448.f : 1.f;
+    float acc = 0.f, eacc = 0.f;
+    for (int t = lane; t < DP; t += 64) {
+      float v = t < d ? x[t] : 0.f;
+      uint32_t code = f32_to_e4m3(v / a);
+      Xq[row * DP + t] = (uint8_t)code;
+      float dq = a * e4m3_to_f32(code);
+      acc = __builtin_fmaf(dq, dq, acc);
+      float er = dq - v;
+      eacc = __builtin_fmaf(er, er, eacc);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      acc += __shfl_xor(acc, o);
+      eacc += __shfl_xor(eacc, o);
+    }
+    unsigned long long anybad = ballot(bad);
+    if (lane == 0) {
+      nq[row] = acc;
+      scl[row] = a;
+      float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
+      qerr[row] = e;
+      bad_any |= anybad ? 1u : 0u;
+      max_nq = max(max_nq, __float_as_uint(acc));
+      max_e = max(max_e, __float_as_uint(e));
+    }
+  }
+  __shared__ unsigned red[3][4];
+  if (lane == 0) {
+    red[0][w] = bad_any;
+    red[1][w] = max_nq;
+    red[2][w] = max_e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned b = 0, m1 = 0, m2 = 0;
+    for (int i = 0; i < 4; ++i) {
+      b |= red[0][i];
+      m1 = max(m1, red[1][i]);
+      m2 = max(m2, red[2][i]);
+    }
+    if (b) atomicOr(&gstat[0], 1u);
+    atomicMax(&gstat[1], m1);
+    atomicMax(&gstat[2], m2);
+  }
+}
+
+template <int PREC>
+struct KcT;
+template <>
+struct KcT<FAMST_FP32> {
+  static constexpr int ESZ = 4, FB = 16;   // FB: bytes of one operand fragment per lane
+};
+template <>
+struct KcT<FAMST_BF16> {
+  static constexpr int ESZ = 2, FB = 16;
+};
+template <>
+struct KcT<FAMST_FP8_E4M3> {
+  static constexpr int ESZ = 1, FB = 32;
+};
+constexpr int KCH = 256;   // bytes of a row per K chunk
+
+template <int PREC, int KC>
+__global__ __launch_bounds__(256, (KC == 32 ? 2 : 1)) void dist_topk_kc_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, const float* __restrict__ scl, int DP,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s) {
+  using T = KcT<PREC>;
+  constexpr int QB = 2, QW = 32, QBLK = 128, BN = 64;
+  constexpr int NKBC = KCH / (4 * T::FB);   // k-blocks per chunk
+  constexpr int CPR = KCH / 16;             // 16-byte chunks per staged row
+  const char* Xq = reinterpret_cast<const char*>(Xq_);
+  const int RB = DP * T::ESZ;               // bytes per row in HBM
+  const int nch = RB / KCH;                 // K chunks
+
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  Cand* lst = reinterpret_cast<Cand*>(smem);                 // [QBLK][KC]
+  char* tq = reinterpret_cast<char*>(lst + QBLK * KC);        // [QBLK][KCH] query chunk
+  char* tt = tq + QBLK * KCH;                                 // [BN][KCH] tile chunk
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;
+  for (int e = tid; e < QBLK * KC; e += 256) lst[e] = Cand{F_INF, 0x7FFFFFFF};
+  float nqq[QB], U[QB], aq[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    int q = wq0 + qb * 16 + i16;
+    bool ok = q < bd.q1;
+    nqq[qb] = ok ? nq[q] : 0.f;
+    U[qb] = ok ? F_INF : -F_INF;
+    aq[qb] = (PREC == FAMST_FP8_E4M3 && ok) ? scl[q] : 1.f;
+  }
+  __syncthreads();
+
+  for (int t0 = bd.c0; t0 < bd.c1; t0 += BN) {
+    f32x4 acc[QB][4];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < nch; ++ch) {
+      // stage the query chunk (128 rows) and the tile chunk (64 rows)
+      for (int c = tid; c < (QBLK + BN) * CPR; c += 256) {
+        int r = c / CPR, cc = c - r * CPR;
+        int64_t row;
+        bool ok;
+        char* dst;
+        if (r < QBLK) {
+          row = bd.q0 + r;
+          ok = row < bd.q1;
+          dst = tq + r * KCH + ((cc ^ (r & 15)) << 4);
+        } else {
+          int rr = r - QBLK;
+          row = t0 + rr;
+          ok = row < bd.c1;
+          dst = tt + rr * KCH + ((cc ^ (rr & 15)) << 4);
+        }
+        i32x4 v = {0, 0, 0, 0};
+        if (ok) v = *reinterpret_cast<const i32x4*>(Xq + row * RB + (int64_t)ch * KCH + cc * 16);
+        *reinterpret_cast<i32x4*>(dst) = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kb = 0; kb < NKBC; ++kb) {
+        const int c0 = (kb * 4 * T::FB + g * T::FB) >> 4;   // first 16-byte chunk of this lane's fragment
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+          const int ra = jb * 16 + i16;
+          if constexpr (T::FB == 16) {
+            i32x4 a = *reinterpret_cast<const i32x4*>(tt + ra * KCH + ((c0 ^ (ra & 15)) << 4));
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) {
+              const int rq = wave * QW + qb * 16 + i16;
+              i32x4 b = *reinterpret_cast<const i32x4*>(tq + rq * KCH + ((c0 ^ (rq & 15)) << 4));
+              if constexpr (PREC == FAMST_FP32) {
+                f32x4 af = __builtin_bit_cast(f32x4, a), bf = __builtin_bit_cast(f32x4, b);
+                acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
+                acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
+                acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
+                acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
+              } else {
+                acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc[qb][jb], 0, 0, 0);
+              }
+            }
+          } else {
+            i32x4 a0 = *reinterpret_cast<const i32x4*>(tt + ra * KCH + ((c0 ^ (ra & 15)) << 4));
+            i32x4 a1 = *reinterpret_cast<const i32x4*>(tt + ra * KCH + (((c0 + 1) ^ (ra & 15)) << 4));
+            i32x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) {
+              const int rq = wave * QW + qb * 16 + i16;
+              i32x4 b0 = *reinterpret_cast<const i32x4*>(tq + rq * KCH + ((c0 ^ (rq & 15)) << 4));
+              i32x4 b1 = *reinterpret_cast<const i32x4*>(tq + rq * KCH + (((c0 + 1) ^ (rq & 15)) << 4));
+              i32x8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+              acc[qb][jb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[qb][jb], 0, 0, 0, 127, 0, 127);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // filter: rows t0 + jb*16 + 4g + r of this lane
+    float nqj[4][4], cj[4][4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = t0 + jb * 16 + 4 * g + r;
+        bool ok = row < bd.c1;
+        nqj[jb][r] = ok ? nq[row] : F_INF;
+        cj[jb][r] = -2.f * ((PREC == FAMST_FP8_E4M3 && ok) ? scl[row] : 1.f);
+      }
+    unsigned qbmask = 0;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      float m = F_INF;
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m = fminf(m, __builtin_fmaf(cj[jb][r] * aq[qb], acc[qb][jb][r], nqj[jb][r]));
+      qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+    }
+    if (qbmask)
+      insert_candidates<QB, KC>(lst + wave * QW * KC, qbmask, U, nqq,
+                                [&](int qb, int e) {
+                                  return __builtin_fmaf(cj[e >> 2][e & 3] * aq[qb], acc[qb][e >> 2][e & 3],
+                                                        nqj[e >> 2][e & 3]);
+                                },
+                                t0, bd.c1, wq0, lane, g, i16);
+  }
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     for (int qq = 0; qq < 16; ++qq) {
@@ -473,7 +753,8 @@ __global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict_
 
 // --------------------------------------------------------------- host side
 struct KnnPlan {
-  int prec, KC, DP, nkb, QB, qblk;
+  int prec, KC, DP, nkb, QB, qblk, esz;
+  bool chunked;   // K-chunked kernel (any d, float8) instead of resident queries
   size_t lds;
 };
 
@@ -482,17 +763,49 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.KC = k_cand ? k_cand : (k <= 24 ? 32 : 64);
   if (p.KC != 32 && p.KC != 64) return FAMST_EINVAL;
   if (p.KC < k) return FAMST_EINVAL;
+  p.esz = prec == FAMST_FP32 ? 4 : (prec == FAMST_BF16 ? 2 : 1);
   const int kbw = prec == FAMST_FP32 ? 16 : 32;
   p.nkb = (d + kbw - 1) / kbw;
-  p.DP = p.nkb * kbw;
-  const int nkb_max = prec == FAMST_FP32 ? 8 : 8;
-  if (p.nkb > nkb_max) return FAMST_ENOTIMPL;
-  p.QB = (p.KC == 64) ? 2 : 4;
-  p.qblk = 64 * p.QB;
-  const int esz = prec == FAMST_FP32 ? 4 : 2;
-  p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * esz;
+  p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
+  if (!p.chunked) {
+    p.DP = p.nkb * kbw;
+    p.QB = (p.KC == 64) ? 2 : 4;
+    p.qblk = 64 * p.QB;
+    p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
+  } else {
+    const int cdim = KCH / p.esz;               // dims per K chunk
+    p.DP = (d + cdim - 1) / cdim * cdim;
+    p.QB = 2;
+    p.qblk = 128;
+    p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)(128 + 64) * KCH;
+  }
   if (p.lds > 160 * 1024) return FAMST_ENOTIMPL;
   return FAMST_OK;
+}
+
+template <int PREC, int KC>
+static int launch_kc(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                     const float* scl, const BlockDesc* desc, int* cj, float* cs) {
+  auto kern = dist_topk_kc_kernel<PREC, KC>;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, scl, p.DP, desc, cj, cs);
+}
+
+static int dispatch_kc(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                       const float* scl, const BlockDesc* desc, int* cj, float* cs) {
+  if (p.prec == FAMST_FP32)
+    return p.KC == 32 ? launch_kc<FAMST_FP32, 32>(p, nblk, s, Xq, nq, scl, desc, cj, cs)
+                      : launch_kc<FAMST_FP32, 64>(p, nblk, s, Xq, nq, scl, desc, cj, cs);
+  if (p.prec == FAMST_BF16)
+    return p.KC == 32 ? launch_kc<FAMST_BF16, 32>(p, nblk, s, Xq, nq, scl, desc, cj, cs)
+                      : launch_kc<FAMST_BF16, 64>(p, nblk, s, Xq, nq, scl, desc, cj, cs);
+  return p.KC == 32 ? launch_kc<FAMST_FP8_E4M3, 32>(p, nblk, s, Xq, nq, scl, desc, cj, cs)
+                    : launch_kc<FAMST_FP8_E4M3, 64>(p, nblk, s, Xq, nq, scl, desc, cj, cs);
 }
 
 template <int PREC, int NKB, int QB, int KC>
@@ -539,7 +852,6 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   const bool exact = (precision & FAMST_EXACT) != 0;
   if ((precision & ~(0xFF | FAMST_EXACT)) != 0) return FAMST_EINVAL;
   if (prec != FAMST_FP32 && prec != FAMST_BF16 && prec != FAMST_FP8_E4M3) return FAMST_EINVAL;
-  if (prec == FAMST_FP8_E4M3) return FAMST_ENOTIMPL;
   int64_t one[2] = {0, n};
   const int64_t* offs = offs_h ? offs_h : one;
   if (!offs_h && B != 1) return FAMST_EINVAL;
@@ -553,11 +865,12 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   FAMST_TRY(choose_plan(prec, d, k, k_cand, p));
   int nblk = 0;
   for (int b = 0; b < B; ++b) nblk += (int)cdiv(offs[b + 1] - offs[b], p.qblk);
-  const int esz = prec == FAMST_FP32 ? 4 : 2;
+  const int esz = p.esz;
 
   Carve cv(ws);
   void* Xq = cv.take<char>((size_t)n * p.DP * esz);
   float* nq = cv.take<float>(n);
+  float* scl = cv.take<float>(n);
   float* qerr = cv.take<float>(n);
   unsigned* gstat = cv.take<unsigned>(4);
   BlockDesc* desc = cv.take<BlockDesc>(nblk);
@@ -591,18 +904,24 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   delete[] hd;
   if (e1 || e2 || e3 || e4 || e5 || e6) return FAMST_EHIP;
 
+  const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
   if (prec == FAMST_FP32)
-    FAMST_TRY(launch("prep", prep_kernel<FAMST_FP32>, dim3(std::min<unsigned>(cdiv(n, 4), 4096)), dim3(256), 0, s, X, n, d,
-                     p.DP, Xq, nq, qerr, gstat));
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_FP32>, pgrid, dim3(256), 0, s, X, n, d, p.DP, Xq, nq,
+                     qerr, gstat));
+  else if (prec == FAMST_BF16)
+    FAMST_TRY(launch("prep", prep_kernel<FAMST_BF16>, pgrid, dim3(256), 0, s, X, n, d, p.DP, Xq, nq,
+                     qerr, gstat));
   else
-    FAMST_TRY(launch("prep", prep_kernel<FAMST_BF16>, dim3(std::min<unsigned>(cdiv(n, 4), 4096)), dim3(256), 0, s, X, n, d,
-                     p.DP, Xq, nq, qerr, gstat));
+    FAMST_TRY(launch("prep", prep_fp8_kernel, pgrid, dim3(256), 0, s, X, n, d, p.DP,
+                     reinterpret_cast<uint8_t*>(Xq), scl, nq, qerr, gstat));
   unsigned bad_flag = 0;
   FAMST_HIP(hipMemcpyAsync(&bad_flag, gstat, 4, hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
   if (bad_flag) return FAMST_ENONFINITE;
 
-  if (prec == FAMST_FP32)
+  if (p.chunked)
+    FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
+  else if (prec == FAMST_FP32)
     FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs));
   else
     FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs));

@@ -70,16 +70,32 @@ __global__ void edge_compact_kernel(const uint64_t* __restrict__ keys, const uin
 }
 
 // ------------------------------------------------------------- Boruvka
+// Live edges only (ids in `live`): drop edges inside one component, and
+// lower the per-component minimum key; a plain read first skips the atomic
+// for the (common) edges that cannot improve it.
 __global__ void bv_min_edge_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
-                                   const uint32_t* __restrict__ ewb, int64_t m,
-                                   const int32_t* __restrict__ comp, unsigned long long* __restrict__ best) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
+                                   const uint32_t* __restrict__ ewb, const uint32_t* __restrict__ live,
+                                   int64_t nlive, const int32_t* __restrict__ comp,
+                                   unsigned long long* __restrict__ best, int64_t* __restrict__ keep) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlive) return;
+  const uint32_t e = live[i];
   int cu = comp[elo[e]], cv = comp[ehi[e]];
-  if (cu == cv) return;
+  if (cu == cv) {
+    keep[i] = 0;
+    return;
+  }
+  keep[i] = 1;
   unsigned long long key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
-  atomicMin(&best[cu], key);
-  atomicMin(&best[cv], key);
+  if (key < __hip_atomic_load(&best[cu], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&best[cu], key);
+  if (key < __hip_atomic_load(&best[cv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&best[cv], key);
+}
+
+__global__ void bv_compact_kernel(const uint32_t* __restrict__ live, const int64_t* __restrict__ keep,
+                                  const int64_t* __restrict__ pos, int64_t nlive,
+                                  uint32_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nlive && keep[i]) out[pos[i]] = live[i];
 }
 
 __global__ void bv_hook_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
@@ -554,6 +570,8 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   int32_t* ehi = cv.take<int32_t>(m0);
   uint32_t* ewb = cv.take<uint32_t>(m0);
   uint8_t* in_tree = cv.take<uint8_t>(m0);
+  uint32_t* liveA = cv.take<uint32_t>(m0);
+  uint32_t* liveB = cv.take<uint32_t>(m0);
   int32_t* comp = cv.take<int32_t>(n);
   int32_t* P = cv.take<int32_t>(n);
   unsigned long long* best = cv.take<unsigned long long>(n);
@@ -591,20 +609,33 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   FAMST_HIP(hipMemsetAsync(in_tree, 0, m, s));
   if (algo == FAMST_BORUVKA) {
     FAMST_TRY(iota_i32(comp, n, s));
-    for (int round = 0; round < 64; ++round) {
+    FAMST_TRY(iota_i32(reinterpret_cast<int32_t*>(liveA), m, s));
+    uint32_t* cur = liveA;
+    uint32_t* nxt = liveB;
+    int64_t nlive = m;
+    for (int round = 0; round < 64 && nlive > 0; ++round) {
       FAMST_TRY(fill_u64(reinterpret_cast<uint64_t*>(best), KEY_NONE, n, s));
       FAMST_HIP(hipMemsetAsync(hooked, 0, sizeof(int), s));
-      FAMST_TRY(launch("boruvka_min", bv_min_edge_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, elo,
-                       ehi, ewb, m, comp, best));
+      FAMST_TRY(launch("boruvka_min", bv_min_edge_kernel, dim3(cdiv(nlive, 256)), dim3(256), 0, s, elo,
+                       ehi, ewb, cur, nlive, comp, best, flag));
       FAMST_TRY(launch("boruvka_hook", bv_hook_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, elo, ehi,
                        n, comp, best, P, in_tree, hooked));
       FAMST_TRY(launch("boruvka_jump", bv_jump_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, comp, n,
                        P));
       FAMST_TRY(launch("boruvka_relabel", bv_relabel_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, comp,
                        P, n));
+      // drop edges that were inside one component before this round's hooks
+      FAMST_HIP(hipMemsetAsync(flag + nlive, 0, sizeof(int64_t), s));
+      FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, nlive + 1, s));
+      FAMST_TRY(launch("boruvka_compact", bv_compact_kernel, dim3(cdiv(nlive, 256)), dim3(256), 0, s,
+                       cur, flag, pos, nlive, nxt));
       int hh = 0;
+      int64_t nl = 0;
       FAMST_HIP(hipMemcpyAsync(&hh, hooked, sizeof(int), hipMemcpyDeviceToHost, s));
+      FAMST_HIP(hipMemcpyAsync(&nl, pos + nlive, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       FAMST_HIP(hipStreamSynchronize(s));
+      std::swap(cur, nxt);
+      nlive = nl;
       if (!hh) break;
     }
   } else {

@@ -101,3 +101,30 @@ def test_knn_deterministic():
     a = _run(X, 10, precision="fp32", exact=True)
     b = _run(X, 10, precision="fp32", exact=True)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec,d", [("fp32", 200), ("bf16", 300), ("fp8", 64), ("fp8", 130), ("bf16", 960)])
+def test_knn_chunked_and_fp8_exact_mode_matches_oracle(prec, d):
+    # d beyond the register-resident kernel, and float8 at any d, use the
+    # K-chunked kernel; exact mode must still give the exact neighbour sets
+    print(f"case prec={prec} d={d}", flush=True)
+    X = datagen.blobs(n=1500, d=d, n_clusters=6, seed=d)
+    nbr, dist, st = _run(X, 12, precision=prec, exact=True)
+    print("stats", st)
+    _check_exact(X, 12, nbr, dist)
+
+
+def test_knn_lowrank_d960_precisions():
+    # the 960-dimensional embedding-like workload at a size the oracle covers
+    X = datagen.lowrank(n=6000, d=960, seed=0)
+    ref_n, _ = oracle.knn_exact(X, 20)
+    rec = {}
+    for prec in ["fp32", "bf16", "fp8"]:
+        nbr, dist, st = _run(X, 20, precision=prec, exact=False)
+        rec[prec] = oracle.recall_at_k(nbr, ref_n)
+        print(prec, "recall", rec[prec], st)
+    assert rec["fp32"] == 1.0
+    assert rec["bf16"] >= 0.98
+    assert rec["fp8"] >= 0.9
+    nbr, dist, st = _run(X, 20, precision="fp8", exact=True)
+    _check_exact(X, 20, nbr, dist)

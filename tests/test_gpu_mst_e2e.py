@@ -188,3 +188,14 @@ def test_errors():
     with pytest.raises(F.FamstError) as ei:
         F.knn_graph(Xn, 3)
     assert ei.value.code == -6
+
+
+def test_famst_lowrank_d960_fp8_and_bf16_weight_error():
+    X = datagen.lowrank(n=5000, d=960, seed=1)
+    ref = oracle.famst(X, 20, 10, seed=0)
+    Xd = _dev(X, torch.float32)
+    for prec, tol in [("fp32", 1e-5), ("bf16", 1e-3), ("fp8", 1e-3)]:
+        out = F.famst(Xd, 20, 10, seed=0, precision=prec, exact=(prec == "fp32"))
+        W = float(out.W[0].item())
+        print(prec, "W", W, "oracle", ref.W, "rel", abs(W - ref.W) / ref.W)
+        assert abs(W - ref.W) / ref.W <= tol
