@@ -124,32 +124,31 @@ __device__ __forceinline__ void insert_candidates(Cand* wl, unsigned qbmask, flo
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     if (!(qbmask & (1u << qb))) continue;
-    float sp[16];
+    const int q = wq0 + qb * 16 + i16;   // this lane's query in block qb
+    f32x16 sp;
     unsigned pm = 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       sp[e] = spf(qb, e);
-      pm |= (sp[e] <= U[qb] ? 1u : 0u) << e;
+      const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
+      const bool ok = (sp[e] <= U[qb]) & (j < c1) & (j != q);
+      pm |= (ok ? 1u : 0u) << e;
     }
     while (true) {
-      unsigned long long lanes = ballot(pm != 0);
+      const unsigned long long lanes = ballot(pm != 0);
       if (!lanes) break;
       const int src = __builtin_ctzll(lanes);
       const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
-      if (lane == src) pm &= pm - 1;
-      float v = sp[0];
-#pragma unroll
-      for (int x = 1; x < 16; ++x) v = (e == x) ? sp[x] : v;
+      pm = (lane == src) ? (pm & (pm - 1)) : pm;
+      const float v = sp[e];   // uniform index into a register vector
       const float spv = readlane_f(v, src);
       if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
       const int qi = qb * 16 + (src & 15);                 // query within wave
       const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
-      const int q = wq0 + qi;
-      if (j >= c1 || j == q) continue;
       const float s = spv + readlane_f(nqq[qb], src);
       Cand* L = wl + qi * KC;
-      Cand c = lane < KC ? L[lane] : Cand{F_INF, 0x7FFFFFFF};
-      const bool lt = lane < KC && key_less(c.s, c.j, s, j);
+      const Cand c = L[lane & (KC - 1)];
+      const bool lt = (lane < KC) & ((c.s < s) | ((c.s == s) & (c.j < j)));
       const int pos = __builtin_popcountll(ballot(lt));
       if (pos >= KC) continue;
       // shift the tail up by one: lane l takes lane l-1's entry (DPP wave_shr:1)
@@ -161,9 +160,8 @@ __device__ __forceinline__ void insert_candidates(Cand* wl, unsigned qbmask, flo
       if (lane < KC) L[lane] = nc;
       const float Tn = readlane_f(nc.s, KC - 1);
       // a few ulps of slack so rounding in U never hides an equal key
-      float Un = Tn - nqq[qb];
-      Un = Un + fabsf(Tn) * 2.4e-7f;
-      if (i16 == (src & 15)) U[qb] = Un;
+      const float Un = (Tn - readlane_f(nqq[qb], src)) + fabsf(Tn) * 2.4e-7f;
+      U[qb] = (i16 == (src & 15)) ? Un : U[qb];
     }
   }
 }
