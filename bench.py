@@ -72,6 +72,62 @@ def time_path(F, torch, Xd, k, lam, seed, rounds, precision, exact, steps, warmu
     return (t1 - t0) * 1000.0 / steps, out, phases
 
 
+def bench_clouds(args, F, torch):
+    """Batched clouds: the exact tree weight + gradient of every cloud in one
+    persistent launch, and the k = 16 FAMST path over the same batch."""
+    import datagen
+    X, offs = datagen.clouds(n_clouds=256, lo=512, hi=8192, d=64, seed=0)
+    n, d = X.shape
+    Xd = torch.from_numpy(X).to("cuda:0")
+    gW = torch.ones(len(offs) - 1, device=Xd.device)
+
+    def exact_step():
+        return F.mst_dense_fused(Xd, offs=offs)
+
+    def knn_step():
+        out = F.famst(Xd, 16, 5, seed=args.seed, max_rounds=args.rounds, precision="bf16", exact=False,
+                      offs=offs)
+        g = F.mst_backward(Xd, out.tu, out.tv, gW, offs=offs)
+        return out, g
+
+    res = {}
+    for name, fn, kern in [("exact", exact_step, "dense_prim_fused"), ("k16", knn_step, "dist_topk")]:
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        F.profile_reset()
+        F.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F.profile_enable(False)
+        nl, ms = F.profile_read(kern)
+        res[name] = {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "kernel": kern,
+                     "kernel_avg_ms": ms / nl if nl else None}
+    # exact path: Prim over all pairs is sum n_i^2 * d fused multiply-adds of distance work
+    sizes = np.diff(offs)
+    prim_flops = float(np.sum(sizes.astype(np.float64) ** 2)) * d * 2.0
+    ex = res["exact"]
+    val = n / (ex["ms_per_step"] * 1e-3)
+    alu = prim_flops / (ex["kernel_avg_ms"] * 1e-3) / 1e12 if ex["kernel_avg_ms"] else None
+    return {
+        "metric": "points/s to approx MST at stated weight error, BF16/FP8+rerank vs FP32",
+        "value": round(val, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ex["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "clouds-256-d64", "clouds": len(sizes), "n_total": int(n), "d": d,
+                   "mode": "exact tree (k = n_i - 1) + gradient, one persistent launch"},
+        "roofline": {"bound": "alu", "achieved": round(alu, 2) if alu else None, "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": round(alu / 157.3, 4) if alu else None, "traffic": None,
+                     "kernel": "dense_prim_fused", "algorithmic_flops": prim_flops},
+        "k16_path": {"ms_per_step": round(res["k16"]["ms_per_step"], 3),
+                     "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1)},
+        "cpu_baseline": None,
+    }
+
+
 def cpu_baseline(X, k, rows):
     import oracle
     t0 = time.perf_counter()
@@ -85,7 +141,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gamma-int-1m-d128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gamma-int-1m-d128", choices=sorted(WORKLOADS) + ["clouds-256-d64"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--fp32-steps", type=int, default=1)
@@ -105,6 +161,9 @@ def main():
     import paper_2507_14261_amd as F
 
     F.load()
+    if args.workload == "clouds-256-d64":
+        print(json.dumps(bench_clouds(args, F, torch)), flush=True)
+        return
     gen_name, kw, k, lam = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     X = getattr(datagen, gen_name)(seed=0, **kw)
@@ -132,6 +191,26 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12 if nl else None
     nlf, totf = phases_f.get("dist_topk", {}).get("launches", 0), phases_f.get("dist_topk", {}).get("total_ms", 0.0)
     avg_f = totf / nlf if nlf else float("nan")
+
+    # achieved bandwidth of the gather / streaming kernels (algorithmic bytes)
+    KC = 32 if k <= 24 else 64
+    ncol = int(out_b.graph.col.numel())
+    mdeg = ncol / n
+    nE = len(out_b.E)
+    gbytes = {
+        "prep": n * d * 4 + n * d * 2 + 8 * n,
+        "rerank": n * (KC + 1) * d * 4 + n * k * 8,
+        "refine": out_b.rounds * nE * (2 * mdeg + 2) * d * 4,
+        "mst_backward": (n + 2 * (n - 1)) * d * 4 + n * d * 4,
+    }
+    bw = {}
+    for name, b in gbytes.items():
+        ph = phases_b.get(name)
+        if ph and ph["total_ms"] > 0:
+            per_launch_ms = ph["total_ms"] / args.steps
+            gbs = b / (per_launch_ms * 1e-3) / 1e9
+            bw[name] = {"algorithmic_GB": round(b / 1e9, 3), "ms_per_step": round(per_launch_ms, 3),
+                        "GB_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / HBM_GBS, 4)}
 
     # sampled exact-kNN parity at full size + the CPU oracle baseline
     rng = np.random.default_rng(1)
@@ -179,6 +258,7 @@ def main():
                       "dist_topk_avg_ms": round(avg_f, 3),
                       "dist_topk_tflops": round(flops / (avg_f * 1e-3) / 1e12, 2) if nlf else None,
                       "frac_of_fp32_peak": round(flops / (avg_f * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4) if nlf else None},
+        "bandwidth_bf16_path": bw,
         "phases_ms_bf16": phases_b,
         "phases_ms_fp32": phases_f,
         "parity": parity,

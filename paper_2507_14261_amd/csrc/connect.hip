@@ -270,7 +270,8 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   FAMST_TRY(launch("comp_label", comp_label_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, parent,
                    lab, n, comp, ckey, vidx));
   // per-cloud component counts: lab at the cloud offsets
-  FAMST_TRY(launch("gather", gather_i64_kernel, dim3(1), dim3(256), 0, s, lab, offs_d, B + 1, gath));
+  FAMST_TRY(launch("gather", gather_i64_kernel, dim3(cdiv(B + 1, 256)), dim3(256), 0, s, lab, offs_d,
+                   B + 1, gath));
   std::vector<int64_t> cbase(B + 1);
   int hbad = 0;
   int64_t ncol = 0;
@@ -281,6 +282,11 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   FAMST_TRY(sort_pairs_u32_i32(tmp, tmpb, ckey, skey, vidx, members, n, bits_for(n + 1), s));
   FAMST_HIP(hipStreamSynchronize(s));
   if (hbad) return FAMST_EINVAL;
+  // every cloud holds at least one component and at most its size
+  for (int b = 0; b < B; ++b) {
+    const int64_t t = cbase[b + 1] - cbase[b];
+    if (cbase[b] < 0 || t < 1 || t > offs[b + 1] - offs[b]) return FAMST_EHIP;
+  }
   const int64_t T = cbase[B];
   FAMST_TRY(launch("comp_ptr", comp_ptr_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, skey, n, T,
                    comp_ptr));

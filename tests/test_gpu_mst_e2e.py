@@ -199,3 +199,29 @@ def test_famst_lowrank_d960_fp8_and_bf16_weight_error():
         W = float(out.W[0].item())
         print(prec, "W", W, "oracle", ref.W, "rel", abs(W - ref.W) / ref.W)
         assert abs(W - ref.W) / ref.W <= tol
+
+
+def test_famst_batched_clouds_k16_per_cloud():
+    # the batched-clouds workload at reduced size: every cloud is its own
+    # FAMST problem, the cloud index enters the random-edge counter
+    X, offs = datagen.clouds(n_clouds=6, lo=200, hi=1500, d=32, seed=11)
+    print("case clouds=6 k=16 lam=5 sizes", np.diff(offs).tolist(), flush=True)
+    refs = oracle.famst_batched(X, offs, 16, 5, seed=4)
+    Xd = _dev(X, torch.float32)
+    for prec, tol in [("fp32", 1e-5), ("bf16", 1e-3)]:
+        out = F.famst(Xd, 16, 5, seed=4, precision=prec, exact=(prec == "fp32"), offs=offs)
+        W = out.W.cpu().numpy()
+        tu, tv = out.tu.cpu().numpy(), out.tv.cpu().numpy()
+        assert len(tu) == len(X) - 6
+        for b, ref in enumerate(refs):
+            assert abs(float(W[b]) - ref.W) / ref.W <= tol, (prec, b)
+            lo, hi = offs[b], offs[b + 1]
+            inb = (tu >= lo) & (tu < hi)
+            assert np.all((tv[inb] >= lo) & (tv[inb] < hi))
+            assert int(inb.sum()) == hi - lo - 1
+        if prec == "fp32":
+            # refinement runs until every cloud is settled: per-round totals
+            # are the sums of the clouds' own change counts
+            R = max(len(r.deltas) for r in refs)
+            tot = [sum(r.deltas[i] if i < len(r.deltas) else 0 for r in refs) for i in range(R)]
+            assert out.deltas[:R] == tot

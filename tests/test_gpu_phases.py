@@ -97,6 +97,37 @@ def test_lambda_edges_batched_use_cloud_counter():
         base += len(comps_ref)
 
 
+@pytest.mark.parametrize("n_clouds", [255, 256, 600])
+def test_connect_many_clouds(n_clouds):
+    # more clouds than one block of threads: per-cloud component offsets
+    # must be gathered for every cloud
+    print(f"case n_clouds={n_clouds}", flush=True)
+    X, offs = datagen.clouds(n_clouds=n_clouds, lo=6, hi=40, d=4, n_clusters=3, seed=n_clouds)
+    k, lam, seed = 1, 2, 5
+    nbr = np.concatenate([oracle.knn_exact(X[offs[b]:offs[b + 1]], k)[0] + offs[b]
+                          for b in range(n_clouds)])
+    G, E = _connect(X, nbr, lam, seed, offs=offs)
+    comp = G.comp.cpu().numpy()
+    u, v, w, a, b = _edges_np(E)
+    got = _pair_sets(u, v, a, b)
+    base, P = 0, 0
+    for cb in range(n_clouds):
+        sl = slice(offs[cb], offs[cb + 1])
+        comp_ref, comps_ref = oracle.components(oracle.undirected_graph(nbr[sl] - offs[cb]))
+        t = len(comps_ref)
+        assert G.n_comp[cb] == t
+        np.testing.assert_array_equal(comp[sl], comp_ref + base)
+        if cb % 37 == 0:
+            Eref = oracle.random_edges(X[sl], comps_ref, lam, seed, cloud=cb)
+            ref = _pair_sets(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base, Eref.b + base)
+            for key, val in ref.items():
+                assert got[key] == val
+        base += t
+        P += t * (t - 1) // 2
+    assert len(u) == lam * P
+    assert G.comp_ptr.cpu().numpy()[base] == len(X)
+
+
 def _edges_to_oracle(u, v, w, a, b):
     return oracle.EdgeSet(u.astype(np.int64), v.astype(np.int64), (w.astype(np.float64)) ** 2,
                           a.astype(np.int64), b.astype(np.int64))
