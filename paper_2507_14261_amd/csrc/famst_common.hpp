@@ -84,25 +84,45 @@ __device__ __forceinline__ int readlane_i(int v, int l) {
 }
 
 // Relative error bound of the float32 direct-difference squared distance
-// computed by sq32_group below: each of 16 lanes sums ceil(d/16) products
-// with fused multiply-adds, then 4 pairwise additions, and the differences
-// are rounded once.  Doubled for safety margin.
+// computed by sq32_group below: each of 16 lanes sums at most
+// 4 ceil(d/64) products with fused multiply-adds, then 4 pairwise
+// additions, and the differences are rounded once.  Doubled for safety
+// margin.
 __host__ __device__ inline float tau32(int d) {
-  int m = (d + 15) / 16;
+  int m = 4 * ((d + 63) / 64);
   return 2.0f * (float)(m + 4 + 2) * 5.9604645e-8f;  // 2^-24
 }
 
-// Canonical float32 squared distance by direct difference.  Evaluated by a
-// group of 16 consecutive lanes (r = lane within the group): lane r sums
-// dimensions r, r+16, r+32, ... with fmaf, then a fixed xor-butterfly over
-// the 16 lanes.  Every lane of the group returns the same bits, and
-// sq32(a, b) == sq32(b, a) exactly because (a-b)^2 == (b-a)^2.
+// Canonical float32 squared distance by direct difference.  The dimensions
+// form chunks of four (chunk c = dimensions 4c .. 4c+3); partial sum r
+// (r = 0..15) runs over chunks r, r+16, r+32, ... in ascending dimension
+// order with fmaf, and the 16 partials are combined pairwise as
+// ((p0+p8)+(p4+p12)) + ((p2+p10)+(p6+p14)) + ... , i.e. an xor butterfly
+// over 8, 4, 2, 1.  Every kernel that needs a float32 distance produces
+// exactly these bits, whatever its lane mapping (IEEE addition is
+// commutative), and sq32(a, b) == sq32(b, a) because (a-b)^2 == (b-a)^2.
+//
+// This version is evaluated by a group of 16 consecutive lanes; lane r owns
+// partial r and all lanes of the group return the same bits.
 __device__ __forceinline__ float sq32_group(const float* __restrict__ a,
                                             const float* __restrict__ b, int d, int r) {
   float acc = 0.f;
-  for (int t = r; t < d; t += 16) {
-    float df = a[t] - b[t];
-    acc = __builtin_fmaf(df, df, acc);
+  const bool vec = (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
+  for (int t0 = 4 * r; t0 < d; t0 += 64) {
+    if (vec && t0 + 4 <= d) {
+      const f32x4 xa = *reinterpret_cast<const f32x4*>(a + t0);
+      const f32x4 xb = *reinterpret_cast<const f32x4*>(b + t0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float df = xa[i] - xb[i];
+        acc = __builtin_fmaf(df, df, acc);
+      }
+    } else {
+      for (int t = t0; t < t0 + 4 && t < d; ++t) {
+        const float df = a[t] - b[t];
+        acc = __builtin_fmaf(df, df, acc);
+      }
+    }
   }
   acc += __shfl_xor(acc, 8, 16);
   acc += __shfl_xor(acc, 4, 16);
@@ -116,10 +136,11 @@ __device__ __forceinline__ float sq32_group(const float* __restrict__ a,
 __device__ __forceinline__ double sq64_group(const float* __restrict__ a,
                                              const float* __restrict__ b, int d, int r) {
   double acc = 0.0;
-  for (int t = r; t < d; t += 16) {
-    double df = (double)a[t] - (double)b[t];
-    acc = __builtin_fma(df, df, acc);
-  }
+  for (int t0 = 4 * r; t0 < d; t0 += 64)
+    for (int t = t0; t < t0 + 4 && t < d; ++t) {
+      double df = (double)a[t] - (double)b[t];
+      acc = __builtin_fma(df, df, acc);
+    }
   acc += __shfl_xor(acc, 8, 16);
   acc += __shfl_xor(acc, 4, 16);
   acc += __shfl_xor(acc, 2, 16);

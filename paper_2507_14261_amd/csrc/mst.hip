@@ -226,10 +226,11 @@ __global__ __launch_bounds__(256) void tree_weight_kernel(const float* __restric
 }
 
 // ------------------------------------------------------------ dense Prim
-// Exact tree of the complete graph of one cloud per block: the
-// distances to the newest tree vertex are computed on the fly, so nothing
-// of size n^2 is stored.  Keys are (w, min, max) as everywhere.
-constexpr int PRIM_MAX = 16384;
+// Exact tree of the complete graph of one cloud: the distances to the newest
+// tree vertex are computed on the fly, so nothing of size n^2 is stored.
+// Keys are (w, min, max) as everywhere.
+constexpr int PRIM_MAX = 16384;   // local ids fit in 14 bits
+constexpr int PRIM_NT = 512;      // threads per cloud
 
 __device__ __forceinline__ bool ekey_less(float w1, int a1, int b1, float w2, int a2, int b2) {
   int l1 = min(a1, b1), h1 = max(a1, b1), l2 = min(a2, b2), h2 = max(a2, b2);
@@ -238,80 +239,168 @@ __device__ __forceinline__ bool ekey_less(float w1, int a1, int b1, float w2, in
   return h1 < h2;
 }
 
-__global__ __launch_bounds__(256) void prim_kernel(const float* __restrict__ X, int d,
-                                                   const int64_t* __restrict__ offs,
-                                                   int32_t* __restrict__ ou, int32_t* __restrict__ ov,
-                                                   float* __restrict__ ow) {
+// Four lanes (a quad) evaluate one canonical distance (the bits of
+// sq32_group): lane c owns partials c, c+4, c+8 and c+12, i.e. the chunks
+// congruent to c mod 4, so a quad reads each 64-byte stretch of a row with
+// one 16-byte load per lane.  The partials are combined in the lane
+// ((pc + pc+8) + (pc+4 + pc+12)), then across the quad by xor 2 and xor 1.
+template <int CTRL>
+__device__ __forceinline__ float quad_xor_add(float v) {
+  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false);
+  return v + __int_as_float(o);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+
+__device__ __forceinline__ float quad_combine(const float (&p)[4]) {
+  const float s4 = (p[0] + p[2]) + (p[1] + p[3]);
+  return quad_xor_add<DPP_QUAD_XOR1>(quad_xor_add<DPP_QUAD_XOR2>(s4));
+}
+
+// partials of lane c for any d (scalar loads; dimensions past d are skipped)
+__device__ __forceinline__ void quad_partials(const float* __restrict__ a, const float* __restrict__ b,
+                                              int d, int c, float (&p)[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) p[m] = 0.f;
+  for (int base = 0; base < d; base += 64)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int t0 = base + 4 * (c + 4 * m);
+      for (int t = t0; t < t0 + 4 && t < d; ++t) {
+        const float df = a[t] - b[t];
+        p[m] = __builtin_fmaf(df, df, p[m]);
+      }
+    }
+}
+
+// Selection key of a candidate edge (w, p, j), w >= 0, local ids < 2^14:
+// ordered as (w, min, max); the low bit says whether j (the vertex outside
+// the tree) is the smaller endpoint.
+__device__ __forceinline__ uint64_t prim_key(float w, int p, int j) {
+  const uint32_t lo = (uint32_t)min(p, j), hi = (uint32_t)max(p, j);
+  return ((uint64_t)__float_as_uint(w) << 29) | ((uint64_t)lo << 15) | ((uint64_t)hi << 1) |
+         (uint64_t)(j < p);
+}
+
+// Dense Prim over rows c0 .. c0 + nb - 1 by PRIM_NT threads.  Quad g owns
+// the points j = g + NQ i: only its lanes touch bw[j] (best weight to the
+// tree, -1 once in the tree) and par[j] (its tree endpoint), and lane 0 of
+// the quad writes them, so one barrier per step suffices: the per-wave
+// minimum keys go through LDS (double-buffered by step parity) and every
+// thread reduces them in the same order.  emit(step, p, j, w) is called by
+// thread 0 for each edge, in insertion order.  VEC: d == 64 and rows
+// 16-byte aligned; four rows per quad are in flight.
+template <bool VEC, class Emit>
+__device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int nb,
+                           float* __restrict__ bw, int* __restrict__ par,
+                           uint64_t* __restrict__ wkeys, Emit emit) {
+  constexpr int NW = PRIM_NT / 64, NQ = PRIM_NT / 4, R = 4;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, c = t & 3, g = t >> 2;
+  for (int j = t; j < nb; j += PRIM_NT) {
+    bw[j] = j == 0 ? -1.f : F_INF;
+    par[j] = -1;
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int step = 1; step < nb; ++step) {
+    const float* __restrict__ xc = X + (c0 + cur) * d;
+    uint64_t best = ~0ull;
+    auto visit = [&](int j, float w) {
+      float w0 = bw[j];
+      int p0 = par[j];
+      if (p0 < 0 || ekey_less(w, cur, j, w0, p0, j)) {
+        w0 = w;
+        p0 = cur;
+        if (c == 0) {
+          bw[j] = w;
+          par[j] = cur;
+        }
+      }
+      const uint64_t key = prim_key(w0, p0, j);
+      best = key < best ? key : best;
+    };
+    if constexpr (VEC) {
+      f32x4 xa[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) xa[m] = reinterpret_cast<const f32x4*>(xc)[c + 4 * m];
+      for (int j0 = g; j0 < nb; j0 += NQ * R) {
+        bool on[R];
+        f32x4 rv[R][4];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int j = j0 + u * NQ;
+          on[u] = j < nb && bw[j] >= 0.f;
+          // quads without work read the newest vertex's row (cached), so the
+          // loads need no branches
+          const f32x4* row = reinterpret_cast<const f32x4*>(X + (c0 + (on[u] ? j : cur)) * 64);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) rv[u][m] = row[c + 4 * m];
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          float pp[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            float acc = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float df = xa[m][i] - rv[u][m][i];
+              acc = __builtin_fmaf(df, df, acc);
+            }
+            pp[m] = acc;
+          }
+          const float w = __builtin_sqrtf(quad_combine(pp));
+          if (on[u]) visit(j0 + u * NQ, w);
+        }
+      }
+    } else {
+      for (int j = g; j < nb; j += NQ) {
+        if (bw[j] < 0.f) continue;   // uniform in the quad
+        float pp[4];
+        quad_partials(xc, X + (c0 + j) * d, d, c, pp);
+        visit(j, __builtin_sqrtf(quad_combine(pp)));
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint64_t other = __shfl_xor(best, o);
+      best = other < best ? other : best;
+    }
+    uint64_t* wk = wkeys + (step & 1) * NW;
+    if (lane == 0) wk[wave] = best;
+    __syncthreads();
+    best = wk[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) best = wk[w] < best ? wk[w] : best;
+    const int lo = (int)((best >> 15) & 0x3FFF), hi = (int)((best >> 1) & 0x3FFF);
+    const int j = (best & 1) ? lo : hi, p = (best & 1) ? hi : lo;
+    const float w = __uint_as_float((uint32_t)(best >> 29));
+    if (t == 0) emit(step, p, j, w);
+    if (j % NQ == g && c == 0) bw[j] = -1.f;
+    cur = __builtin_amdgcn_readfirstlane(j);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(PRIM_NT) void prim_kernel(const float* __restrict__ X, int d,
+                                                       const int64_t* __restrict__ offs, int vec,
+                                                       int32_t* __restrict__ ou, int32_t* __restrict__ ov,
+                                                       float* __restrict__ ow) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int b = blockIdx.x, t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  __shared__ uint64_t wkeys[2 * PRIM_NT / 64];
+  const int b = blockIdx.x;
   const int64_t c0 = offs[b];
   const int nb = (int)(offs[b + 1] - c0);
-  float* bw = reinterpret_cast<float*>(smem);          // best weight to the tree
-  int* bf = reinterpret_cast<int*>(bw + PRIM_MAX);     // its tree endpoint (local), -1: in tree
-  __shared__ float rw[256];
-  __shared__ int rj[256];
-  __shared__ int cur_s;
-  for (int j = t; j < nb; j += 256) {
-    bw[j] = F_INF;
-    bf[j] = -2;   // -2: not reached yet
-  }
-  __syncthreads();
-  if (t == 0) {
-    bf[0] = -1;
-    cur_s = 0;
-  }
-  __syncthreads();
+  float* bw = reinterpret_cast<float*>(smem);
+  int* par = reinterpret_cast<int*>(bw + PRIM_MAX);
   const int64_t eo = c0 - b;  // output slot of this cloud's first edge
-  for (int step = 1; step < nb; ++step) {
-    const int cur = cur_s;
-    const float* xc = X + (c0 + cur) * d;
-    for (int j = grp; j < nb; j += 16) {
-      if (bf[j] == -1) continue;  // uniform in group
-      float s = sq32_group(xc, X + (c0 + j) * d, d, r16);
-      float w = __builtin_sqrtf(s);
-      if (r16 == 0) {
-        int f = bf[j];
-        if (f == -2 || ekey_less(w, cur, j, bw[j], f, j)) {
-          bw[j] = w;
-          bf[j] = cur;
-        }
-      }
-    }
-    __syncthreads();
-    float mw = F_INF;
-    int mj = -1;
-    for (int j = t; j < nb; j += 256) {
-      if (bf[j] < 0) continue;
-      if (mj < 0 || ekey_less(bw[j], bf[j], j, mw, bf[mj], mj)) {
-        mw = bw[j];
-        mj = j;
-      }
-    }
-    rw[t] = mw;
-    rj[t] = mj;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if (t < w) {
-        int oj = rj[t + w];
-        if (oj >= 0 && (rj[t] < 0 || ekey_less(rw[t + w], bf[oj], oj, rw[t], bf[rj[t]], rj[t]))) {
-          rw[t] = rw[t + w];
-          rj[t] = oj;
-        }
-      }
-      __syncthreads();
-    }
-    if (t == 0) {
-      int j = rj[0];
-      int f = bf[j];
-      int lo = min(f, j), hi = max(f, j);
-      ou[eo + step - 1] = (int32_t)(c0 + lo);
-      ov[eo + step - 1] = (int32_t)(c0 + hi);
-      ow[eo + step - 1] = rw[0];
-      bf[j] = -1;
-      cur_s = j;
-    }
-    __syncthreads();
-  }
+  auto emit = [&](int step, int p, int j, float w) {
+    ou[eo + step - 1] = (int32_t)(c0 + min(p, j));
+    ov[eo + step - 1] = (int32_t)(c0 + max(p, j));
+    ow[eo + step - 1] = w;
+  };
+  if (vec) prim_cloud<true>(X, d, c0, nb, bw, par, wkeys, emit);
+  else prim_cloud<false>(X, d, c0, nb, bw, par, wkeys, emit);
 }
 
 // Persistent exact-tree kernel for a batch of clouds: blocks pull clouds
@@ -322,19 +411,19 @@ __global__ __launch_bounds__(256) void prim_kernel(const float* __restrict__ X, 
 // children in ascending order, so it is deterministic.
 constexpr int FUSED_MAX = 12288;
 
-__global__ __launch_bounds__(256) void prim_fused_kernel(
+__global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
     const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
-    int B, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
+    int B, int vec, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
     float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* bw = reinterpret_cast<float*>(smem);             // best weight to the tree; -1 once in the tree
-  int* par = reinterpret_cast<int*>(bw + FUSED_MAX);      // tree endpoint of that best edge (parent)
+  float* bw = reinterpret_cast<float*>(smem);             // Prim: best weight; later list ends
+  int* par = reinterpret_cast<int*>(bw + FUSED_MAX);      // tree endpoint of the best edge (parent)
   int* kid = par + FUSED_MAX;                             // children lists (after the tree is built)
-  __shared__ float rw[256];
-  __shared__ int rj[256];
-  __shared__ int cur_s, cloud_s;
-  __shared__ float ss[256], ee[256];
+  __shared__ uint64_t wkeys[2 * PRIM_NT / 64];
+  __shared__ float ss[PRIM_NT], ee[PRIM_NT];
+  __shared__ int cloud_s;
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  constexpr int NG = PRIM_NT / 16;
   while (true) {
     if (t == 0) {
       int idx = atomicAdd(queue, 1);
@@ -342,73 +431,25 @@ __global__ __launch_bounds__(256) void prim_fused_kernel(
     }
     __syncthreads();
     const int b = cloud_s;
+    __syncthreads();   // every thread has read cloud_s before it is rewritten
     if (b < 0) break;
     const int64_t c0 = offs[b];
     const int nb = (int)(offs[b + 1] - c0);
     const int64_t eo = c0 - b;
-    for (int j = t; j < nb; j += 256) {
-      bw[j] = F_INF;
-      par[j] = -1;
-    }
-    __syncthreads();
-    if (t == 0) {
-      bw[0] = -1.f;
-      cur_s = 0;
-    }
-    __syncthreads();
     // ---- dense Prim
-    for (int step = 1; step < nb; ++step) {
-      const int cur = cur_s;
-      const float* xc = X + (c0 + cur) * d;
-      for (int j = grp; j < nb; j += 16) {
-        if (bw[j] < 0.f) continue;  // in the tree (uniform in group)
-        float s = sq32_group(xc, X + (c0 + j) * d, d, r16);
-        float w = __builtin_sqrtf(s);
-        if (r16 == 0) {
-          int f = par[j];
-          if (f < 0 || ekey_less(w, cur, j, bw[j], f, j)) {
-            bw[j] = w;
-            par[j] = cur;
-          }
-        }
-      }
-      __syncthreads();
-      float mw = F_INF;
-      int mj = -1;
-      for (int j = t; j < nb; j += 256) {
-        if (bw[j] < 0.f) continue;
-        if (mj < 0 || ekey_less(bw[j], par[j], j, mw, par[mj], mj)) {
-          mw = bw[j];
-          mj = j;
-        }
-      }
-      rw[t] = mw;
-      rj[t] = mj;
-      __syncthreads();
-      for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) {
-          int oj = rj[t + w];
-          if (oj >= 0 && (rj[t] < 0 || ekey_less(rw[t + w], par[oj], oj, rw[t], par[rj[t]], rj[t]))) {
-            rw[t] = rw[t + w];
-            rj[t] = oj;
-          }
-        }
-        __syncthreads();
-      }
-      if (t == 0) {
-        int j = rj[0];
-        ou[eo + step - 1] = (int32_t)(c0 + par[j]);
-        ov[eo + step - 1] = (int32_t)(c0 + j);
-        ow[eo + step - 1] = rw[0];
-        bw[j] = -1.f;
-        cur_s = j;
-      }
-      __syncthreads();
-    }
+    auto emit = [&](int step, int p, int j, float w) {
+      ou[eo + step - 1] = (int32_t)(c0 + p);
+      ov[eo + step - 1] = (int32_t)(c0 + j);
+      ow[eo + step - 1] = w;
+    };
+    if (vec) prim_cloud<true>(X, d, c0, nb, bw, par, wkeys, emit);
+    else prim_cloud<false>(X, d, c0, nb, bw, par, wkeys, emit);
+    __threadfence_block();
+    __syncthreads();
     // ---- tree weight, compensated, in insertion order
     {
       float sacc = 0.f, cacc = 0.f;
-      for (int i = t; i < nb - 1; i += 256) {
+      for (int i = t; i < nb - 1; i += PRIM_NT) {
         float ns, err;
         two_sum(sacc, ow[eo + i], ns, err);
         sacc = ns;
@@ -417,7 +458,7 @@ __global__ __launch_bounds__(256) void prim_fused_kernel(
       ss[t] = sacc;
       ee[t] = cacc;
       __syncthreads();
-      for (int w = 128; w >= 1; w >>= 1) {
+      for (int w = PRIM_NT / 2; w >= 1; w >>= 1) {
         if (t < w) {
           float ns, err;
           two_sum(ss[t], ss[t + w], ns, err);
@@ -431,7 +472,7 @@ __global__ __launch_bounds__(256) void prim_fused_kernel(
     // ---- children lists by counting sort, stable in child id (one thread;
     // bw is reused for the list ends)
     int* endp = reinterpret_cast<int*>(bw);
-    for (int j = t; j < nb; j += 256) endp[j] = 0;
+    for (int j = t; j < nb; j += PRIM_NT) endp[j] = 0;
     __syncthreads();
     if (t == 0) {
       for (int c = 1; c < nb; ++c) endp[par[c]] += 1;
@@ -445,7 +486,7 @@ __global__ __launch_bounds__(256) void prim_fused_kernel(
     }
     __syncthreads();
     // ---- gradient rows, one 16-lane group per row
-    for (int v = grp; v < nb; v += 16) {
+    for (int v = grp; v < nb; v += NG) {
       const float* xv = X + (c0 + v) * d;
       float* out = grad + (c0 + v) * d;
       const int k0 = v == 0 ? 0 : endp[v - 1], k1 = endp[v];
@@ -548,8 +589,9 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
                           hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PRIM_MAX * 4);
       attr = true;
     }
-    FAMST_TRY(launch("dense_prim", prim_kernel, dim3(B), dim3(256), (size_t)2 * PRIM_MAX * 4, s, X, d,
-                     offs_d, pu, pv, pw));
+    const int vec = (d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    FAMST_TRY(launch("dense_prim", prim_kernel, dim3(B), dim3(PRIM_NT), (size_t)2 * PRIM_MAX * 4, s, X,
+                     d, offs_d, vec, pu, pv, pw));
     FAMST_TRY(launch("pair_keys", pair_keys_kernel, dim3(cdiv(nt, 256)), dim3(256), 0, s, pu, pv, pw,
                      nt, k1, v1));
     FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, k1, k2, v1, v2, nt, 32 + bits_for(n), s));
@@ -706,6 +748,7 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
     attr = true;
   }
   const int grid = std::min(B, ncu);
-  return launch("dense_prim_fused", prim_fused_kernel, dim3(grid), dim3(256), lds, s, X, d, offs_d,
-                order_d, B, queue, tu, tv, tw, W, grad_X);
+  const int vec = (d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+  return launch("dense_prim_fused", prim_fused_kernel, dim3(grid), dim3(PRIM_NT), lds, s, X, d, offs_d,
+                order_d, B, vec, queue, tu, tv, tw, W, grad_X);
 }

@@ -85,7 +85,7 @@ def test_tree_batched_clouds():
         assert math.isclose(float(W[b]), RW, rel_tol=2e-7)
 
 
-@pytest.mark.parametrize("n,d", [(300, 8), (1200, 64), (64, 3)])
+@pytest.mark.parametrize("n,d", [(300, 8), (1200, 64), (64, 3), (65, 64), (60, 130), (50, 67), (2000, 128)])
 def test_dense_prim_is_exact_mst(n, d):
     X = datagen.blobs(n=n, d=d, n_clusters=4, seed=n)
     tu, tv, tw, W = F.mst(_dev(X, torch.float32), algo="prim")
