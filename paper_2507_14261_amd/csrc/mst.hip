@@ -275,109 +275,155 @@ __device__ __forceinline__ void quad_partials(const float* __restrict__ a, const
 
 // Selection key of a candidate edge (w, p, j), w >= 0, local ids < 2^14:
 // ordered as (w, min, max); the low bit says whether j (the vertex outside
-// the tree) is the smaller endpoint.
+// the tree) is the smaller endpoint.  ~0 marks a dead list entry.
 __device__ __forceinline__ uint64_t prim_key(float w, int p, int j) {
   const uint32_t lo = (uint32_t)min(p, j), hi = (uint32_t)max(p, j);
   return ((uint64_t)__float_as_uint(w) << 29) | ((uint64_t)lo << 15) | ((uint64_t)hi << 1) |
          (uint64_t)(j < p);
 }
+constexpr uint64_t PRIM_DEAD = ~0ull;
+__device__ __forceinline__ float key_w(uint64_t k) { return __uint_as_float((uint32_t)(k >> 29)); }
+__device__ __forceinline__ int key_j(uint64_t k) {
+  return (k & 1) ? (int)((k >> 15) & 0x3FFF) : (int)((k >> 1) & 0x3FFF);
+}
+__device__ __forceinline__ int key_p(uint64_t k) {
+  return (k & 1) ? (int)((k >> 1) & 0x3FFF) : (int)((k >> 15) & 0x3FFF);
+}
 
-// Dense Prim over rows c0 .. c0 + nb - 1 by PRIM_NT threads.  Quad g owns
-// the points j = g + NQ i: only its lanes touch bw[j] (best weight to the
-// tree, -1 once in the tree) and par[j] (its tree endpoint), and lane 0 of
-// the quad writes them, so one barrier per step suffices: the per-wave
-// minimum keys go through LDS (double-buffered by step parity) and every
-// thread reduces them in the same order.  emit(step, p, j, w) is called by
-// thread 0 for each edge, in insertion order.  VEC: d == 64 and rows
-// 16-byte aligned; four rows per quad are in flight.
-template <bool VEC, class Emit>
+// Candidate update of list entry `key` (vertex j outside the tree) by the
+// distance s to the newest tree vertex cur.  Skips the square root when
+// s > w0^2 (1 + 2^-20): then sqrtf(s) rounds strictly above w0 and the entry
+// cannot change.
+__device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
+  const float w0 = key_w(key);
+  if (s > w0 * w0 * 1.00000095f && w0 > 1e-18f) return key;
+  const float w = __builtin_sqrtf(s);
+  const int j = key_j(key);
+  return ekey_less(w, cur, j, w0, key_p(key), j) ? prim_key(w, cur, j) : key;
+}
+
+// Dense Prim over rows c0 .. c0 + nb - 1 by PRIM_NT threads.  `keys` holds
+// one key per vertex outside the tree (its best edge to the tree); slot q
+// belongs to quad q mod NQ, whose lane 0 alone writes it, so one barrier
+// per step suffices: the per-wave minimum keys go through LDS
+// (double-buffered by step parity) and every thread reduces them in the
+// same order.  The entry of the vertex that joins the tree is marked dead
+// by its owner; every PRIM_COMPACT steps the live entries are packed to the
+// front (their order does not matter: the minimum is over unique keys).
+// emit(step, p, j, w) is called by thread 0 for each edge, in insertion
+// order.  VEC: d == 64 and rows 16-byte aligned; four rows per quad are in
+// flight.  CMAX >= nb / PRIM_NT.
+constexpr int PRIM_COMPACT = 32;
+
+template <bool VEC, int CMAX, class Emit>
 __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int nb,
-                           float* __restrict__ bw, int* __restrict__ par,
-                           uint64_t* __restrict__ wkeys, Emit emit) {
+                           uint64_t* __restrict__ keys, uint64_t* __restrict__ wkeys,
+                           int* __restrict__ mcount, Emit emit) {
   constexpr int NW = PRIM_NT / 64, NQ = PRIM_NT / 4, R = 4;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, c = t & 3, g = t >> 2;
-  for (int j = t; j < nb; j += PRIM_NT) {
-    bw[j] = j == 0 ? -1.f : F_INF;
-    par[j] = -1;
-  }
+  // vertex 0 starts the tree; every other vertex has the placeholder edge
+  // (+inf, 0, j), replaced in the first step
+  for (int j = 1 + t; j < nb; j += PRIM_NT) keys[j - 1] = prim_key(F_INF, 0, j);
+  if (t == 0) *mcount = 0;
   __syncthreads();
+  int m = nb - 1;
   int cur = 0;
   for (int step = 1; step < nb; ++step) {
     const float* __restrict__ xc = X + (c0 + cur) * d;
-    uint64_t best = ~0ull;
-    auto visit = [&](int j, float w) {
-      float w0 = bw[j];
-      int p0 = par[j];
-      if (p0 < 0 || ekey_less(w, cur, j, w0, p0, j)) {
-        w0 = w;
-        p0 = cur;
-        if (c == 0) {
-          bw[j] = w;
-          par[j] = cur;
-        }
-      }
-      const uint64_t key = prim_key(w0, p0, j);
-      best = key < best ? key : best;
-    };
+    uint64_t best = PRIM_DEAD;
+    int bslot = -1;
     if constexpr (VEC) {
       f32x4 xa[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) xa[m] = reinterpret_cast<const f32x4*>(xc)[c + 4 * m];
-      for (int j0 = g; j0 < nb; j0 += NQ * R) {
-        bool on[R];
+      for (int mm = 0; mm < 4; ++mm) xa[mm] = reinterpret_cast<const f32x4*>(xc)[c + 4 * mm];
+      for (int q0 = g; q0 < m; q0 += NQ * R) {
+        uint64_t kk[R];
         f32x4 rv[R][4];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          const int j = j0 + u * NQ;
-          on[u] = j < nb && bw[j] >= 0.f;
-          // quads without work read the newest vertex's row (cached), so the
-          // loads need no branches
-          const f32x4* row = reinterpret_cast<const f32x4*>(X + (c0 + (on[u] ? j : cur)) * 64);
+          const int q = q0 + u * NQ;
+          kk[u] = q < m ? keys[q] : PRIM_DEAD;
+          // dead or missing entries read the newest vertex's row (cached),
+          // so the loads need no branches
+          const int row = kk[u] != PRIM_DEAD ? key_j(kk[u]) : cur;
+          const f32x4* rp = reinterpret_cast<const f32x4*>(X + (c0 + row) * 64);
 #pragma unroll
-          for (int m = 0; m < 4; ++m) rv[u][m] = row[c + 4 * m];
+          for (int mm = 0; mm < 4; ++mm) rv[u][mm] = rp[c + 4 * mm];
         }
 #pragma unroll
         for (int u = 0; u < R; ++u) {
           float pp[4];
 #pragma unroll
-          for (int m = 0; m < 4; ++m) {
+          for (int mm = 0; mm < 4; ++mm) {
             float acc = 0.f;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float df = xa[m][i] - rv[u][m][i];
+              const float df = xa[mm][i] - rv[u][mm][i];
               acc = __builtin_fmaf(df, df, acc);
             }
-            pp[m] = acc;
+            pp[mm] = acc;
           }
-          const float w = __builtin_sqrtf(quad_combine(pp));
-          if (on[u]) visit(j0 + u * NQ, w);
+          const float sq = quad_combine(pp);
+          if (kk[u] != PRIM_DEAD) {
+            const uint64_t nk = prim_relax(kk[u], sq, cur);
+            const int q = q0 + u * NQ;
+            if (nk != kk[u] && c == 0) keys[q] = nk;
+            if (nk < best) {
+              best = nk;
+              bslot = q;
+            }
+          }
         }
       }
     } else {
-      for (int j = g; j < nb; j += NQ) {
-        if (bw[j] < 0.f) continue;   // uniform in the quad
+      for (int q = g; q < m; q += NQ) {
+        const uint64_t k0 = keys[q];
+        if (k0 == PRIM_DEAD) continue;   // uniform in the quad
         float pp[4];
-        quad_partials(xc, X + (c0 + j) * d, d, c, pp);
-        visit(j, __builtin_sqrtf(quad_combine(pp)));
+        quad_partials(xc, X + (c0 + key_j(k0)) * d, d, c, pp);
+        const uint64_t nk = prim_relax(k0, quad_combine(pp), cur);
+        if (nk != k0 && c == 0) keys[q] = nk;
+        if (nk < best) {
+          best = nk;
+          bslot = q;
+        }
       }
     }
+    uint64_t wb = best;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      const uint64_t other = __shfl_xor(best, o);
-      best = other < best ? other : best;
+      const uint64_t other = __shfl_xor(wb, o);
+      wb = other < wb ? other : wb;
     }
     uint64_t* wk = wkeys + (step & 1) * NW;
-    if (lane == 0) wk[wave] = best;
+    if (lane == 0) wk[wave] = wb;
     __syncthreads();
-    best = wk[0];
+    uint64_t gb = wk[0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) best = wk[w] < best ? wk[w] : best;
-    const int lo = (int)((best >> 15) & 0x3FFF), hi = (int)((best >> 1) & 0x3FFF);
-    const int j = (best & 1) ? lo : hi, p = (best & 1) ? hi : lo;
-    const float w = __uint_as_float((uint32_t)(best >> 29));
-    if (t == 0) emit(step, p, j, w);
-    if (j % NQ == g && c == 0) bw[j] = -1.f;
+    for (int w = 1; w < NW; ++w) gb = wk[w] < gb ? wk[w] : gb;
+    const int j = key_j(gb), p = key_p(gb);
+    if (t == 0) emit(step, p, j, key_w(gb));
+    if (best == gb && c == 0) keys[bslot] = PRIM_DEAD;
     cur = __builtin_amdgcn_readfirstlane(j);
+    if (step % PRIM_COMPACT == 0 && step + 1 < nb) {
+      if (t == 0) *mcount = 0;
+      __syncthreads();   // dead marks and key updates done; counter cleared
+      uint64_t e[CMAX];
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < CMAX; ++i) {
+        const int q = t + PRIM_NT * i;
+        e[i] = q < m ? keys[q] : PRIM_DEAD;
+        cnt += e[i] != PRIM_DEAD;
+      }
+      __syncthreads();   // every live entry is in registers
+      int pos = cnt ? atomicAdd(mcount, cnt) : 0;
+#pragma unroll
+      for (int i = 0; i < CMAX; ++i)
+        if (e[i] != PRIM_DEAD) keys[pos++] = e[i];
+      __syncthreads();
+      m = *mcount;
+    }
   }
   __syncthreads();
 }
@@ -388,19 +434,20 @@ __global__ __launch_bounds__(PRIM_NT) void prim_kernel(const float* __restrict__
                                                        float* __restrict__ ow) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ uint64_t wkeys[2 * PRIM_NT / 64];
+  __shared__ int mcount;
   const int b = blockIdx.x;
   const int64_t c0 = offs[b];
   const int nb = (int)(offs[b + 1] - c0);
-  float* bw = reinterpret_cast<float*>(smem);
-  int* par = reinterpret_cast<int*>(bw + PRIM_MAX);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
   const int64_t eo = c0 - b;  // output slot of this cloud's first edge
   auto emit = [&](int step, int p, int j, float w) {
     ou[eo + step - 1] = (int32_t)(c0 + min(p, j));
     ov[eo + step - 1] = (int32_t)(c0 + max(p, j));
     ow[eo + step - 1] = w;
   };
-  if (vec) prim_cloud<true>(X, d, c0, nb, bw, par, wkeys, emit);
-  else prim_cloud<false>(X, d, c0, nb, bw, par, wkeys, emit);
+  constexpr int CM = PRIM_MAX / PRIM_NT;
+  if (vec) prim_cloud<true, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+  else prim_cloud<false, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
 }
 
 // Persistent exact-tree kernel for a batch of clouds: blocks pull clouds
@@ -416,12 +463,13 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
     int B, int vec, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
     float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* bw = reinterpret_cast<float*>(smem);             // Prim: best weight; later list ends
-  int* par = reinterpret_cast<int*>(bw + FUSED_MAX);      // tree endpoint of the best edge (parent)
-  int* kid = par + FUSED_MAX;                             // children lists (after the tree is built)
+  uint64_t* keys = reinterpret_cast<uint64_t*>(smem);              // Prim candidate list
+  int* par = reinterpret_cast<int*>(keys + FUSED_MAX);            // tree parent of each vertex
+  int* endp = reinterpret_cast<int*>(smem);                       // after Prim: list ends ...
+  int* kid = endp + FUSED_MAX;                                    // ... and children lists
   __shared__ uint64_t wkeys[2 * PRIM_NT / 64];
   __shared__ float ss[PRIM_NT], ee[PRIM_NT];
-  __shared__ int cloud_s;
+  __shared__ int cloud_s, mcount;
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
   constexpr int NG = PRIM_NT / 16;
   while (true) {
@@ -437,13 +485,16 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
     const int nb = (int)(offs[b + 1] - c0);
     const int64_t eo = c0 - b;
     // ---- dense Prim
+    if (t == 0) par[0] = -1;
     auto emit = [&](int step, int p, int j, float w) {
+      par[j] = p;
       ou[eo + step - 1] = (int32_t)(c0 + p);
       ov[eo + step - 1] = (int32_t)(c0 + j);
       ow[eo + step - 1] = w;
     };
-    if (vec) prim_cloud<true>(X, d, c0, nb, bw, par, wkeys, emit);
-    else prim_cloud<false>(X, d, c0, nb, bw, par, wkeys, emit);
+    constexpr int CM = FUSED_MAX / PRIM_NT;
+    if (vec) prim_cloud<true, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+    else prim_cloud<false, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
     __threadfence_block();
     __syncthreads();
     // ---- tree weight, compensated, in insertion order
@@ -469,9 +520,7 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
       }
       if (t == 0) W[b] = ss[0] + ee[0];
     }
-    // ---- children lists by counting sort, stable in child id (one thread;
-    // bw is reused for the list ends)
-    int* endp = reinterpret_cast<int*>(bw);
+    // ---- children lists by counting sort, stable in child id (one thread)
     for (int j = t; j < nb; j += PRIM_NT) endp[j] = 0;
     __syncthreads();
     if (t == 0) {
@@ -586,12 +635,12 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
     static bool attr = false;
     if (!attr) {
       hipFuncSetAttribute(reinterpret_cast<const void*>(prim_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PRIM_MAX * 4);
+                          hipFuncAttributeMaxDynamicSharedMemorySize, PRIM_MAX * 8);
       attr = true;
     }
     const int vec = (d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-    FAMST_TRY(launch("dense_prim", prim_kernel, dim3(B), dim3(PRIM_NT), (size_t)2 * PRIM_MAX * 4, s, X,
-                     d, offs_d, vec, pu, pv, pw));
+    FAMST_TRY(launch("dense_prim", prim_kernel, dim3(B), dim3(PRIM_NT), (size_t)PRIM_MAX * 8, s, X, d,
+                     offs_d, vec, pu, pv, pw));
     FAMST_TRY(launch("pair_keys", pair_keys_kernel, dim3(cdiv(nt, 256)), dim3(256), 0, s, pu, pv, pw,
                      nt, k1, v1));
     FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, k1, k2, v1, v2, nt, 32 + bits_for(n), s));
