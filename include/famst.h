@@ -60,7 +60,9 @@ extern "C" {
 #define FAMST_EDISCONNECTED (-3)  /* the given edges do not span every cloud   */
 #define FAMST_EHIP          (-4)  /* a HIP runtime call failed                  */
 #define FAMST_ENOTIMPL      (-5)  /* combination not supported                 */
-#define FAMST_ENONFINITE    (-6)  /* X holds a NaN or an infinity              */
+#define FAMST_ENONFINITE    (-6)  /* X holds a NaN or an infinity, or (kNN)
+                                     a row with squared norm above 1e37, where
+                                     float32 distances would overflow        */
 #define FAMST_EWORKSPACE    (-7)  /* *ws_bytes smaller than required or ws
                                      misaligned                                */
 #define FAMST_WNOTCONVERGED   1   /* refinement stopped at max_rounds with

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
       // sqrt rounding and the float32 sum itself: inflate slightly
       float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
       qerr[row] = e;
-      bad_any |= anybad ? 1u : 0u;
+      // squared norms must leave headroom: every screened value and every
+      // float32 distance stays finite when they are below 1e37
+      bad_any |= (anybad || !(acc <= 1e37f)) ? 1u : 0u;
       max_nq = max(max_nq, __float_as_uint(acc));
       max_e = max(max_e, __float_as_uint(e));
     }
@@ -359,6 +361,264 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
   }
 }
 
+// ------------------------------------------- pipelined screening, k' = 32
+// The products, filter and insertion rule of dist_topk_kernel, organised
+// for memory-level parallelism: the per-query lists live in registers,
+// which frees LDS for a ring of PIPE tile stages filled by direct
+// global->LDS loads, so PIPE-1 tiles are in flight while one is consumed and
+// a single barrier per tile suffices.
+//
+// Register lists: query qi (0..63) of a wave owns register pair qi/2 of
+// (ls, lj), lanes 32 (qi & 1) .. 32 (qi & 1) + 31, ascending by (s, j).
+typedef float f32x32 __attribute__((ext_vector_type(32)));
+typedef int i32x32 __attribute__((ext_vector_type(32)));
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+constexpr int PIPE = 4;
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  // gfx9 s_waitcnt: vmcnt in bits [3:0] and [15:14]; expcnt and lgkmcnt at
+  // their maxima (not waited for)
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Screening band above the k-th screened value of a query: wide enough
+// that the re-rank certificate (screening arithmetic error eps, input
+// rounding e = e_q + e_max, float32 near-tie factor tau) holds for every
+// element the filter rejects.  +inf while fewer than k entries exist.
+struct Band {
+  float arith_c, nmax, emax, tau;
+  __device__ __forceinline__ float operator()(float Tk, float nqv, float eqv) const {
+    if (!(Tk < F_INF)) return F_INF;
+    const float e = eqv + emax;
+    const float eps = arith_c * (nqv + nmax);
+    const float r = __builtin_sqrtf(fmaxf(Tk, 0.f));
+    // relative part: the certificate's (1 + 2 tau) and its 1e-6 shrink
+    // factors, with a factor of two to spare
+    return 2.f * eps + 4.f * r * e + 4.f * e * e + (8.f * tau + 1e-5f) * fabsf(Tk);
+  }
+};
+
+// The filter threshold of a query is U = T_k - |x_q|^2 + band(T_k) with T_k
+// the k-th entry of its list (not the last): an element screened above it
+// cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
+// rejected element for the certificate.
+template <int QB, int NE, class SpFn>
+__device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbmask, float (&U)[QB],
+                                            const float (&nqq)[QB], const float (&eqq)[QB],
+                                            const Band& band, int kk, SpFn spf, int t0, int c1,
+                                            int wq0, int lane, int g, int i16) {
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    if (!(qbmask & (1u << qb))) continue;
+    const int q = wq0 + qb * 16 + i16;
+    float sp __attribute__((ext_vector_type(NE)));
+    unsigned pm = 0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      sp[e] = spf(qb, e);
+      const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
+      const bool ok = (sp[e] <= U[qb]) & (j < c1) & (j != q);
+      pm |= (ok ? 1u : 0u) << e;
+    }
+    while (true) {
+      const unsigned long long lanes = ballot(pm != 0);
+      if (!lanes) break;
+      const int src = __builtin_ctzll(lanes);
+      const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
+      pm = (lane == src) ? (pm & (pm - 1)) : pm;
+      const float spv = readlane_f(sp[e], src);
+      if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
+      const int qi = qb * 16 + (src & 15);
+      const int L = qi >> 1, h = qi & 1;
+      const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
+      const float s = spv + readlane_f(nqq[qb], src);
+      const float cs = ls[L];
+      const int cjv = lj[L];
+      const bool mine = half == h;
+      const bool lt = mine & ((cs < s) | ((cs == s) & (cjv < j)));
+      const int pos = __builtin_popcountll(ballot(lt));
+      if (pos >= 32) continue;
+      // shift the tail of the half up by one (DPP wave_shr:1); the first lane
+      // of a half never takes the shifted value
+      const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cs), 0x138, 0xF, 0xF, false));
+      const int upj = __builtin_amdgcn_update_dpp(0, cjv, 0x138, 0xF, 0xF, false);
+      const bool keep = !mine | (rel < pos);
+      const float ns = keep ? cs : (rel == pos ? s : ups);
+      const int nj = keep ? cjv : (rel == pos ? j : upj);
+      ls[L] = ns;
+      lj[L] = nj;
+      const float Tk = readlane_f(ns, 32 * h + kk - 1);
+      const float nqv = readlane_f(nqq[qb], src);
+      const float Un = (Tk - nqv) + band(Tk, nqv, readlane_f(eqq[qb], src));
+      U[qb] = (i16 == (src & 15)) ? Un : U[qb];
+    }
+  }
+}
+
+template <int PREC, int NKB>
+__global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
+    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
+    float tau, float* __restrict__ ubound) {
+  using S = Scr<PREC>;
+  constexpr int QB = 4, KC = 32, QW = 64, BN = 64;
+  constexpr int TILE = BN * NKB * 64;   // 64 rows x NKB 64-byte chunks
+  constexpr int STG = TILE + 256;       // tile + its 64 norms
+  const char* Xb = reinterpret_cast<const char*>(Xq_);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;
+  const int RS = nkb * 64, cpr = nkb * 4;
+  const int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
+
+  // resident query fragments
+  i32x4 qf[QB][NKB];
+  float nqq[QB], eqq[QB], U[QB];
+  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = wq0 + qb * 16 + i16;
+    const bool ok = q < bd.q1;
+    nqq[qb] = ok ? nq[q] : 0.f;
+    eqq[qb] = ok ? qerr[q] : 0.f;
+    U[qb] = ok ? F_INF : -F_INF;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      i32x4 v = {0, 0, 0, 0};
+      if (ok && kb < nkb) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
+      qf[qb][kb] = v;
+    }
+  }
+  f32x32 ls;
+  i32x32 lj;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    ls[L] = F_INF;
+    lj[L] = 0x7FFFFFFF;
+  }
+
+  // Loads of tile `it` into stage it % PIPE: chunk slot p of the stage holds
+  // chunk (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
+  // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
+  // its slot.  Every thread issues NKB + 1 loads per tile (padding slots
+  // and rows past the cloud re-read valid data), which keeps the vmcnt
+  // bookkeeping static.
+  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
+  auto issue = [&](int it) {
+    const int t0 = bd.c0 + it * BN;
+    char* stage = smem + (it % PIPE) * STG;
+#pragma unroll
+    for (int i = 0; i < NKB; ++i) {
+      const int p = tid + 256 * i;
+      int r = p / cpr, sc = p - r * cpr;
+      if (i >= nkb) r = sc = 0;
+      const int row = min(t0 + r, bd.c1 - 1);
+      const char* src = Xb + (int64_t)row * RS + ((sc ^ (r & smask)) << 4);
+      char* dst = stage + (256 * i + 64 * wave) * 16;
+      __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 0, 0);
+    }
+    const int row = min(t0 + lane, bd.c1 - 1);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + row), (lptr_t)(stage + TILE), 4, 0, 0);
+  };
+#pragma unroll
+  for (int it = 0; it < PIPE - 1; ++it) issue(it);
+
+  for (int it = 0; it < ntile; ++it) {
+    wait_vmcnt<(PIPE - 2) * (NKB + 1)>();   // this thread's loads of tile it are done
+    __builtin_amdgcn_s_barrier();           // ... and every thread's; tile it-1 is consumed
+    issue(it + PIPE - 1);                   // into the stage tile it-1 used
+    const int t0 = bd.c0 + it * BN;
+    const char* tile = smem + (it % PIPE) * STG;
+    const float* tn = reinterpret_cast<const float*>(tile + TILE);
+    // two halves of 32 rows: half the accumulators are live at a time
+#pragma unroll
+    for (int jh = 0; jh < 2; ++jh) {
+      float nqj[2][4];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * jh + jj) * 16 + 4 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
+      }
+      f32x4 acc[QB][2];
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) acc[qb][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        if (kb < nkb) {
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            const int r = (2 * jh + jj) * 16 + i16;
+            const int cc = kb * 4 + g;
+            const i32x4 a = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) {
+              if constexpr (PREC == FAMST_FP32) {
+                const f32x4 af = __builtin_bit_cast(f32x4, a);
+                const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jj], 0, 0, 0);
+                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jj], 0, 0, 0);
+                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jj], 0, 0, 0);
+                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jj], 0, 0, 0);
+              } else {
+                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+      // screening filter: lane holds rows t0h + jj*16 + 4g + r, query qb*16 + i16
+      const int t0h = t0 + 32 * jh;
+      unsigned qbmask = 0;
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        float m = F_INF;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m = fminf(m, __builtin_fmaf(-2.f, acc[qb][jj][r], nqj[jj][r]));
+        qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+      }
+      if (qbmask)
+        insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, eqq, band, kk,
+                           [&](int qb, int e) {
+                             return __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
+                           },
+                           t0h, bd.c1, wq0, lane, g, i16);
+    }
+  }
+  wait_vmcnt<0>();   // no load may land in LDS after the block ends
+
+  // ---- write the candidate lists and the bound of the rejected elements
+  if (g == 0) {
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int q = wq0 + qb * 16 + i16;
+      if (q < bd.q1) ubound[q] = U[qb] + nqq[qb];
+    }
+  }
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    const int q = wq0 + 2 * L + half;
+    if (q < bd.q1) {
+      cand_s[(int64_t)q * KC + rel] = ls[L];
+      cand_j[(int64_t)q * KC + rel] = lj[L];
+    }
+  }
+}
+
 // ------------------------------------------------ K-chunked screening
 // For any d and for float8: the cloud is streamed in 64-row tiles and the
 // dimension in 256-byte chunks; both the tile chunk and the block's query
@@ -436,7 +696,9 @@ __global__ __launch_bounds__(256) void prep_fp8_kernel(const float* __restrict__
       scl[row] = a;
       float e = eacc > 0.f ? __builtin_sqrtf(eacc) * 1.0001f + 1e-30f : 0.f;
       qerr[row] = e;
-      bad_any |= anybad ? 1u : 0u;
+      // squared norms must leave headroom: every screened value and every
+      // float32 distance stays finite when they are below 1e37
+      bad_any |= (anybad || !(acc <= 1e37f)) ? 1u : 0u;
       max_nq = max(max_nq, __float_as_uint(acc));
       max_e = max(max_e, __float_as_uint(e));
     }
@@ -638,6 +900,7 @@ struct RerankArgs {
   const float* qerr;
   const unsigned* gstat;
   float arith_c;          // screening arithmetic error factor (x 2^-24 folded in)
+  const float* ubound;    // per-query bound of the rejected screened values (or null)
   int* nbr;
   float* dist;
   float* kth_s;           // s of the k-th selected (for recomputation)
@@ -651,10 +914,29 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
   const int t = threadIdx.x;
   const int cb = find_cloud(a.offs, a.B, q);
   const int64_t nb = a.offs[cb + 1] - a.offs[cb];
-  const int L = (int)min<int64_t>(a.KC, nb - 1);
+  const int Lmax = (int)min<int64_t>(a.KC, nb - 1);
   const float* xq = a.X + q * a.d;
   const float tau = tau32(a.d);
-  if (t < L) sm.id[t] = a.cand_j[q * a.KC + t];
+  const int64_t c0 = a.offs[cb];
+  // slots the screening never filled hold (+inf, INT_MAX) and sort last
+  const int jraw = t < Lmax ? a.cand_j[q * a.KC + t] : 0x7FFFFFFF;
+  int L = __builtin_popcountll(ballot(jraw != 0x7FFFFFFF));
+  __shared__ int invalid;
+  if (t == 0) invalid = 0;
+  __syncthreads();
+  const int need = (int)min<int64_t>(a.k, nb - 1);
+  if (t < max(L, need)) {
+    // an id outside the cloud (or too few candidates) is reported: the row is
+    // then uncertified, and the id is replaced so that nothing reads out of
+    // bounds
+    int j = t < L ? jraw : -1;
+    if (j < c0 || j >= c0 + nb || j == q) {
+      invalid = 1;
+      j = q == c0 ? (int)c0 + 1 : (int)c0;
+    }
+    sm.id[t] = j;
+  }
+  L = max(L, need);
   __syncthreads();
   const int grp = t >> 4, r16 = t & 15;
   for (int c = grp; c < L; c += 4) {
@@ -677,9 +959,11 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
     a.kth_s[q] = kth;
     if (tie) atomicAdd(&a.counters[2], 1ull);
     bool cert = true;
-    if (nb - 1 > a.KC) {
-      // every non-candidate j has screened value >= S' (the list maximum)
+    if (nb - 1 > L) {
+      // every non-candidate j has screened value >= S': the list maximum, or
+      // the filter bound of the screening kernel when it reports one
       float Sp = a.cand_s[q * a.KC + a.KC - 1];
+      if (a.ubound) Sp = fminf(Sp, a.ubound[q]);
       float nmax = __uint_as_float(a.gstat[1]);
       float emax = __uint_as_float(a.gstat[2]);
       float eps = a.arith_c * (a.nq[q] + nmax);
@@ -689,7 +973,7 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
       float lb = rr > 0.f ? rr * rr * (1.0f - 1e-6f) : 0.f;
       cert = lb > kth * (1.0f + 2.0f * tau);
     }
-    if (!cert) {
+    if (!cert || invalid) {
       unsigned long long p = atomicAdd(&a.counters[0], 1ull);
       a.bad_rows[p] = (int)q;
     }
@@ -753,6 +1037,7 @@ __global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict_
 struct KnnPlan {
   int prec, KC, DP, nkb, QB, qblk, esz;
   bool chunked;   // K-chunked kernel (any d, float8) instead of resident queries
+  bool piped;     // register lists + pipelined tiles (k' = 32, up to 128 bf16 / 64 fp32 dims)
   size_t lds;
 };
 
@@ -765,11 +1050,17 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   const int kbw = prec == FAMST_FP32 ? 16 : 32;
   p.nkb = (d + kbw - 1) / kbw;
   p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
+  p.piped = false;
   if (!p.chunked) {
     p.DP = p.nkb * kbw;
     p.QB = (p.KC == 64) ? 2 : 4;
     p.qblk = 64 * p.QB;
     p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
+    if (p.KC == 32 && p.nkb <= 4) {
+      const int nk = p.nkb <= 1 ? 1 : (p.nkb <= 2 ? 2 : 4);
+      p.piped = true;
+      p.lds = (size_t)PIPE * (64 * nk * 64 + 256);
+    }
   } else {
     const int cdim = KCH / p.esz;               // dims per K chunk
     p.DP = (d + cdim - 1) / cdim * cdim;
@@ -820,9 +1111,37 @@ static int launch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
                 cj, cs);
 }
 
+// Inputs of the k-band filter of the pipelined kernel.
+struct BandArgs {
+  int k;
+  const float* qerr;
+  const unsigned* gstat;
+  float arith_c, tau;
+  float* ubound;
+};
+
+template <int PREC, int NKB>
+static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                     const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
+  auto kern = dist_topk_v2_kernel<PREC, NKB>;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
+                ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
+}
+
 template <int PREC>
 static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
-                       const BlockDesc* desc, int* cj, float* cs) {
+                       const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
+  if (p.piped) {
+    if (p.nkb <= 1) return launch_v2<PREC, 1>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+    if (p.nkb <= 2) return launch_v2<PREC, 2>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+    return launch_v2<PREC, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+  }
 #define DT_CASE(NKB)                                                                        \
   if (p.nkb <= NKB) {                                                                       \
     if (p.KC == 32) return launch_dt<PREC, NKB, 4, 32>(p, nblk, s, Xq, nq, desc, cj, cs);   \
@@ -876,6 +1195,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   int* cj = cv.take<int>((size_t)n * p.KC);
   float* cs = cv.take<float>((size_t)n * p.KC);
   float* kth = cv.take<float>(n);
+  float* ub = cv.take<float>(n);
   int* bad = cv.take<int>(n);
   unsigned long long* ctr = cv.take<unsigned long long>(4);
   int* ovf = cv.take<int>(1);
@@ -917,18 +1237,21 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   FAMST_HIP(hipStreamSynchronize(s));
   if (bad_flag) return FAMST_ENONFINITE;
 
+  // matrix-core dot products and norms: |err| <= (2d + 8) 2^-24 (|x|^2 + |y|^2)
+  const float arith_c = (float)(2 * p.DP + 8) * 5.9604645e-8f;
+  const BandArgs ba{k, qerr, gstat, arith_c, tau32(d), ub};
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
   else if (prec == FAMST_FP32)
-    FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs));
+    FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
   else
-    FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs));
+    FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
 
   RerankArgs ra;
   ra.X = X; ra.n = n; ra.d = d; ra.offs = offs_d; ra.B = B; ra.k = k; ra.KC = p.KC;
   ra.cand_j = cj; ra.cand_s = cs; ra.nq = nq; ra.qerr = qerr; ra.gstat = gstat;
-  // matrix-core dot products and norms: |err| <= (2d + 8) 2^-24 (|x|^2 + |y|^2)
-  ra.arith_c = (float)(2 * p.DP + 8) * 5.9604645e-8f;
+  ra.arith_c = arith_c;
+  ra.ubound = p.piped ? ub : nullptr;
   ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_rows = bad; ra.counters = ctr;
   FAMST_TRY(launch("rerank", rerank_kernel, dim3((unsigned)n), dim3(64), 0, s, ra));
 

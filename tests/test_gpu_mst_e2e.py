@@ -188,6 +188,13 @@ def test_errors():
     with pytest.raises(F.FamstError) as ei:
         F.knn_graph(Xn, 3)
     assert ei.value.code == -6
+    # finite, but squared norms beyond float32 headroom
+    Xb = X.clone()
+    Xb[7] = 1e19
+    for prec in ("fp32", "bf16", "fp8"):
+        with pytest.raises(F.FamstError) as ei:
+            F.knn_graph(Xb, 3, precision=prec)
+        assert ei.value.code == -6
 
 
 def test_famst_lowrank_d960_fp8_and_bf16_weight_error():
