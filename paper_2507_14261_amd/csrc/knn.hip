@@ -1078,8 +1078,8 @@ static int launch_kc(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
   auto kern = dist_topk_kc_kernel<PREC, KC>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, scl, p.DP, desc, cj, cs);
@@ -1103,8 +1103,8 @@ static int launch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
   auto kern = dist_topk_kernel<PREC, NKB, QB, KC>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.DP, p.nkb, desc,
@@ -1126,8 +1126,8 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
   auto kern = dist_topk_v2_kernel<PREC, NKB>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,

@@ -634,8 +634,8 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
     FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
     static bool attr = false;
     if (!attr) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(prim_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, PRIM_MAX * 8);
+      FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(prim_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, PRIM_MAX * 8));
       attr = true;
     }
     const int vec = (d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
@@ -792,8 +792,8 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   static bool attr = false;
   const size_t lds = (size_t)3 * FUSED_MAX * 4;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(prim_fused_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(prim_fused_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
   const int grid = std::min(B, ncu);
