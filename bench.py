@@ -24,6 +24,39 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
 HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch) scaled by what the same
+# counters read for a plain copy of known size (FETCH x 2.0, WRITE x 1.0).
+# Valid only for the kernel sources they were taken on: the sha1 of those
+# files is checked at run time and the figure is reported as null after any
+# change.  The summaries and commands are in profiles/.
+MEASURED_TRAFFIC = {
+    ("dist_topk", "gamma-int-1m-d128"): {
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "8e312419af3d9d0d7c6c52640737d3c066fa85d7",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
+        "fetch_GB": 338.0, "write_GB": 0.260,
+        "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
+    ("dense_prim_fused", "clouds-256-d64"): {
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "1c70f182e21003b20c3d1fbecc40b396b7318c57",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
+        "fetch_GB": 799.0, "write_GB": None,
+        "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
+}
+
+
+def measured_traffic(kernel, workload):
+    """HBM GB per launch measured by the counters, or None if the kernel's
+    sources changed since (or no measurement exists)."""
+    import hashlib
+    m = MEASURED_TRAFFIC.get((kernel, workload))
+    if m is None:
+        return None
+    for rel, sha in m["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != sha:
+                return None
+    return round(m["fetch_GB"] + (m["write_GB"] or 0.0), 3)
+
 # workload name -> (generator kwargs, k, lambda)
 WORKLOADS = {
     "gamma-int-1m-d128": ("gamma_int", dict(n=1_000_000, d=128), 20, 10),
@@ -106,12 +139,13 @@ def bench_clouds(args, F, torch):
         nl, ms = F.profile_read(kern)
         res[name] = {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "kernel": kern,
                      "kernel_avg_ms": ms / nl if nl else None}
-    # exact path: Prim over all pairs is sum n_i^2 * d fused multiply-adds of distance work
-    sizes = np.diff(offs)
-    prim_flops = float(np.sum(sizes.astype(np.float64) ** 2)) * d * 2.0
+    # exact path: every Prim step streams the rows still outside the tree, so
+    # one launch reads sum_i n_i (n_i - 1) / 2 rows of d float32 values
+    sizes = np.diff(offs).astype(np.float64)
+    prim_bytes = float(np.sum(sizes * (sizes - 1) / 2)) * d * 4
     ex = res["exact"]
     val = n / (ex["ms_per_step"] * 1e-3)
-    alu = prim_flops / (ex["kernel_avg_ms"] * 1e-3) / 1e12 if ex["kernel_avg_ms"] else None
+    gbs = prim_bytes / (ex["kernel_avg_ms"] * 1e-3) / 1e9 if ex["kernel_avg_ms"] else None
     return {
         "metric": "points/s to approx MST at stated weight error, BF16/FP8+rerank vs FP32",
         "value": round(val, 1), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -119,9 +153,12 @@ def bench_clouds(args, F, torch):
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": "clouds-256-d64", "clouds": len(sizes), "n_total": int(n), "d": d,
                    "mode": "exact tree (k = n_i - 1) + gradient, one persistent launch"},
-        "roofline": {"bound": "alu", "achieved": round(alu, 2) if alu else None, "peak": 157.3,
-                     "unit": "TFLOP/s", "frac": round(alu / 157.3, 4) if alu else None, "traffic": None,
-                     "kernel": "dense_prim_fused", "algorithmic_flops": prim_flops},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_GBS, 4) if gbs else None,
+                     "traffic": measured_traffic("dense_prim_fused", "clouds-256-d64"),
+                     "traffic_unit": "GB per launch", "kernel": "dense_prim_fused",
+                     "avg_ms": round(ex["kernel_avg_ms"], 3) if ex["kernel_avg_ms"] else None,
+                     "algorithmic_GB": round(prim_bytes / 1e9, 3)},
         "k16_path": {"ms_per_step": round(res["k16"]["ms_per_step"], 3),
                      "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1)},
         "cpu_baseline": None,
@@ -249,7 +286,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                      "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_TFLOPS["bf16"], 4) if achieved else None,
-                     "traffic": None, "kernel": "dist_topk", "avg_ms": round(avg_ms, 3),
+                     "traffic": measured_traffic("dist_topk", args.workload), "traffic_unit": "GB per launch",
+                     "kernel": "dist_topk", "avg_ms": round(avg_ms, 3),
                      "algorithmic_flops": flops},
         "cpu_baseline": cpu,
         "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf},
