@@ -117,9 +117,12 @@ def bench_clouds(args, F, torch):
     def exact_step():
         return F.mst_dense_fused(Xd, offs=offs)
 
+    e_cap = [None]
+
     def knn_step():
         out = F.famst(Xd, 16, 5, seed=args.seed, max_rounds=args.rounds, precision="bf16", exact=False,
-                      offs=offs)
+                      offs=offs, e_cap=e_cap[0])
+        e_cap[0] = max(1, len(out.E))
         g = F.mst_backward(Xd, out.tu, out.tv, gW, offs=offs)
         return out, g
 

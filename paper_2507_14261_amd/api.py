@@ -125,7 +125,9 @@ def connect(X, nbr, lam: int, seed: int = 0, offs=None, e_cap: int | None = None
     n_col = ctypes.c_int64(0)
     n_comp = (ctypes.c_int32 * B)()
     n_edges = ctypes.c_int64(0)
-    cap = int(e_cap) if e_cap is not None else max(1, lam * 64)
+    # first guess: a few dozen component pairs per cloud (too small a guess
+    # costs a second pass over the graph, see the ECAPACITY retry below)
+    cap = int(e_cap) if e_cap is not None else lam * (64 + 32 * B)
     E = _empty_edges(cap, dev)
     for attempt in range(2):
         code, _ = _workspace(lib.famst_connect, _ptr(X), n, d, _offs_ptr(o), B, _ptr(nbr), k, lam,

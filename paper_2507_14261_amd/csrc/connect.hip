@@ -53,12 +53,19 @@ __global__ void csr_fill_kernel(const uint64_t* __restrict__ keys, const int64_t
 // ------------------------------------------------------ components
 // Lock-free union-find: a root is only ever hooked under a smaller root, so
 // parent[x] <= x always holds and the final root of a component is its
-// minimum vertex.
+// minimum vertex.  Finds halve the path: a non-root x is re-pointed to its
+// grandparent, an ancestor in the same set.  Hooks only ever replace the
+// parent of a root (compare-and-swap against the root itself), and a
+// non-root never becomes a root again, so these plain stores cannot undo a
+// hook.
 __device__ __forceinline__ int uf_find(int* parent, int x) {
   while (true) {
-    int p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (p == x) return x;
-    x = p;
+    const int gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp == p) return p;
+    __hip_atomic_store(&parent[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = gp;
   }
 }
 
