@@ -383,20 +383,27 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// Screening band above the k-th screened value of a query: wide enough
+// Screening band above the k-th screened value T of a query: wide enough
 // that the re-rank certificate (screening arithmetic error eps, input
 // rounding e = e_q + e_max, float32 near-tie factor tau) holds for every
-// element the filter rejects.  +inf while fewer than k entries exist.
+// element the filter rejects:
+//   band(T) = (2 eps + 4 e^2) + 4 e sqrt(T) + (8 tau + 1e-5) |T|,
+// +inf while fewer than k entries exist.  Only the chance of certifying
+// depends on it: the certificate itself uses the final threshold, which
+// bounds every rejected element whatever the band was.
 struct Band {
   float arith_c, nmax, emax, tau;
-  __device__ __forceinline__ float operator()(float Tk, float nqv, float eqv) const {
-    if (!(Tk < F_INF)) return F_INF;
+  // per-query constants: c0 = 2 eps + 4 e^2, c1 = 4 e
+  __device__ __forceinline__ void consts(float nqv, float eqv, float& c0, float& c1) const {
     const float e = eqv + emax;
-    const float eps = arith_c * (nqv + nmax);
-    const float r = __builtin_sqrtf(fmaxf(Tk, 0.f));
-    // relative part: the certificate's (1 + 2 tau) and its 1e-6 shrink
-    // factors, with a factor of two to spare
-    return 2.f * eps + 4.f * r * e + 4.f * e * e + (8.f * tau + 1e-5f) * fabsf(Tk);
+    c0 = 2.f * arith_c * (nqv + nmax) + 4.f * e * e;
+    c1 = 4.f * e;
+  }
+  __device__ __forceinline__ float operator()(float Tk, float c0, float c1) const {
+    if (!(Tk < F_INF)) return F_INF;
+    // hardware square root, rounded up by a few ulps
+    const float r = c1 > 0.f ? __builtin_amdgcn_sqrtf(fmaxf(Tk, 0.f)) * 1.000001f : 0.f;
+    return c0 + c1 * r + (8.f * tau + 1e-5f) * fabsf(Tk);
   }
 };
 
@@ -404,56 +411,63 @@ struct Band {
 // the k-th entry of its list (not the last): an element screened above it
 // cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
 // rejected element for the certificate.
+//
+// Elements are taken element-major: for each of the NE elements a lane
+// holds (a static register), a ballot gives the lanes whose element passed,
+// and each is inserted in turn into its query's list (a ballot gives the
+// position, DPP wave_shr:1 shifts the tail, the query's threshold follows
+// the new k-th entry).
 template <int QB, int NE, class SpFn>
 __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbmask, float (&U)[QB],
-                                            const float (&nqq)[QB], const float (&eqq)[QB],
-                                            const Band& band, int kk, SpFn spf, int t0, int c1,
-                                            int wq0, int lane, int g, int i16) {
+                                            const float (&nqq)[QB], const float (&bc0)[QB],
+                                            const float (&bc1)[QB], const Band& band, int kk,
+                                            SpFn spf, int t0, int c1, int wq0, int lane, int g,
+                                            int i16) {
   const int half = lane >> 5, rel = lane & 31;
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     if (!(qbmask & (1u << qb))) continue;
     const int q = wq0 + qb * 16 + i16;
-    float sp __attribute__((ext_vector_type(NE)));
-    unsigned pm = 0;
+    float sp[NE];
+    bool ok[NE];
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
       sp[e] = spf(qb, e);
       const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
-      const bool ok = (sp[e] <= U[qb]) & (j < c1) & (j != q);
-      pm |= (ok ? 1u : 0u) << e;
+      ok[e] = (sp[e] <= U[qb]) & (j < c1) & (j != q);
     }
-    while (true) {
-      const unsigned long long lanes = ballot(pm != 0);
-      if (!lanes) break;
-      const int src = __builtin_ctzll(lanes);
-      const int e = __builtin_ctz((unsigned)readlane_i((int)pm, src));
-      pm = (lane == src) ? (pm & (pm - 1)) : pm;
-      const float spv = readlane_f(sp[e], src);
-      if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
-      const int qi = qb * 16 + (src & 15);
-      const int L = qi >> 1, h = qi & 1;
-      const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
-      const float s = spv + readlane_f(nqq[qb], src);
-      const float cs = ls[L];
-      const int cjv = lj[L];
-      const bool mine = half == h;
-      const bool lt = mine & ((cs < s) | ((cs == s) & (cjv < j)));
-      const int pos = __builtin_popcountll(ballot(lt));
-      if (pos >= 32) continue;
-      // shift the tail of the half up by one (DPP wave_shr:1); the first lane
-      // of a half never takes the shifted value
-      const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cs), 0x138, 0xF, 0xF, false));
-      const int upj = __builtin_amdgcn_update_dpp(0, cjv, 0x138, 0xF, 0xF, false);
-      const bool keep = !mine | (rel < pos);
-      const float ns = keep ? cs : (rel == pos ? s : ups);
-      const int nj = keep ? cjv : (rel == pos ? j : upj);
-      ls[L] = ns;
-      lj[L] = nj;
-      const float Tk = readlane_f(ns, 32 * h + kk - 1);
-      const float nqv = readlane_f(nqq[qb], src);
-      const float Un = (Tk - nqv) + band(Tk, nqv, readlane_f(eqq[qb], src));
-      U[qb] = (i16 == (src & 15)) ? Un : U[qb];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      unsigned long long lanes = ballot(ok[e]);
+      while (lanes) {
+        const int src = __builtin_ctzll(lanes);
+        lanes &= lanes - 1;
+        const float spv = readlane_f(sp[e], src);
+        if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
+        const int qi = qb * 16 + (src & 15);
+        const int L = qi >> 1, h = qi & 1;
+        const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
+        const float nqv = readlane_f(nqq[qb], src);
+        const float s = spv + nqv;
+        const float cs = ls[L];
+        const int cjv = lj[L];
+        const bool mine = half == h;
+        const bool lt = mine & ((cs < s) | ((cs == s) & (cjv < j)));
+        const int pos = __builtin_popcountll(ballot(lt));
+        if (pos >= 32) continue;
+        // shift the tail of the half up by one (DPP wave_shr:1); the first
+        // lane of a half never takes the shifted value
+        const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cs), 0x138, 0xF, 0xF, false));
+        const int upj = __builtin_amdgcn_update_dpp(0, cjv, 0x138, 0xF, 0xF, false);
+        const bool keep = !mine | (rel < pos);
+        const float ns = keep ? cs : (rel == pos ? s : ups);
+        const int nj = keep ? cjv : (rel == pos ? j : upj);
+        ls[L] = ns;
+        lj[L] = nj;
+        const float Tk = readlane_f(ns, 32 * h + kk - 1);
+        const float Un = (Tk - nqv) + band(Tk, readlane_f(bc0[qb], src), readlane_f(bc1[qb], src));
+        U[qb] = (i16 == (src & 15)) ? Un : U[qb];
+      }
     }
   }
 }
@@ -481,14 +495,14 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 
   // resident query fragments
   i32x4 qf[QB][NKB];
-  float nqq[QB], eqq[QB], U[QB];
+  float nqq[QB], bc0[QB], bc1[QB], U[QB];
   const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int q = wq0 + qb * 16 + i16;
     const bool ok = q < bd.q1;
     nqq[qb] = ok ? nq[q] : 0.f;
-    eqq[qb] = ok ? qerr[q] : 0.f;
+    band.consts(nqq[qb], ok ? qerr[q] : 0.f, bc0[qb], bc1[qb]);
     U[qb] = ok ? F_INF : -F_INF;
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
@@ -591,7 +605,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
         qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
       }
       if (qbmask)
-        insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, eqq, band, kk,
+        insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, bc0, bc1, band, kk,
                            [&](int qb, int e) {
                              return __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
                            },
