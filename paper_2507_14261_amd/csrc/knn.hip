@@ -490,8 +490,10 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, i16 = lane & 15;
   const int wq0 = bd.q0 + wave * QW;
-  const int RS = nkb * 64, cpr = nkb * 4;
-  const int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
+  // instantiated for the exact number of K-blocks: no runtime guards in the
+  // tile loop (they would split it into branches and force full waits)
+  constexpr int RS = NKB * 64, cpr = NKB * 4;
+  constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
 
   // resident query fragments
   i32x4 qf[QB][NKB];
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
       i32x4 v = {0, 0, 0, 0};
-      if (ok && kb < nkb) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
+      if (ok) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
       qf[qb][kb] = v;
     }
   }
@@ -522,9 +524,8 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   // Loads of tile `it` into stage it % PIPE: chunk slot p of the stage holds
   // chunk (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
   // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
-  // its slot.  Every thread issues NKB + 1 loads per tile (padding slots
-  // and rows past the cloud re-read valid data), which keeps the vmcnt
-  // bookkeeping static.
+  // its slot.  Every thread issues NKB + 1 loads per tile (rows past the
+  // cloud re-read valid data), which keeps the vmcnt bookkeeping static.
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
   auto issue = [&](int it) {
     const int t0 = bd.c0 + it * BN;
@@ -532,8 +533,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 #pragma unroll
     for (int i = 0; i < NKB; ++i) {
       const int p = tid + 256 * i;
-      int r = p / cpr, sc = p - r * cpr;
-      if (i >= nkb) r = sc = 0;
+      const int r = p / cpr, sc = p - r * cpr;
       const int row = min(t0 + r, bd.c1 - 1);
       const char* src = Xb + (int64_t)row * RS + ((sc ^ (r & smask)) << 4);
       char* dst = stage + (256 * i + 64 * wave) * 16;
@@ -567,14 +567,25 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
       for (int qb = 0; qb < QB; ++qb)
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) acc[qb][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+      // A fragments double-buffered: the LDS reads of K-step kb + 1 are issued
+      // before the matrix-core products of K-step kb
+      auto lda = [&](int kb, i32x4 (&a)[2]) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int r = (2 * jh + jj) * 16 + i16;
+          const int cc = kb * 4 + g;
+          a[jj] = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
+        }
+      };
+      i32x4 acur[2], anxt[2];
+      lda(0, acur);
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        if (kb < nkb) {
+        {
+          if (kb + 1 < NKB) lda(kb + 1, anxt);
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) {
-            const int r = (2 * jh + jj) * 16 + i16;
-            const int cc = kb * 4 + g;
-            const i32x4 a = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
+            const i32x4 a = acur[jj];
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) {
               if constexpr (PREC == FAMST_FP32) {
@@ -589,6 +600,10 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
                     __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
               }
             }
+          }
+          if (kb + 1 < NKB) {
+            acur[0] = anxt[0];
+            acur[1] = anxt[1];
           }
         }
       }
@@ -1071,9 +1086,8 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.qblk = 64 * p.QB;
     p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
     if (p.KC == 32 && p.nkb <= 4) {
-      const int nk = p.nkb <= 1 ? 1 : (p.nkb <= 2 ? 2 : 4);
       p.piped = true;
-      p.lds = (size_t)PIPE * (64 * nk * 64 + 256);
+      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256);
     }
   } else {
     const int cdim = KCH / p.esz;               // dims per K chunk
@@ -1152,9 +1166,13 @@ template <int PREC>
 static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                        const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
   if (p.piped) {
-    if (p.nkb <= 1) return launch_v2<PREC, 1>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
-    if (p.nkb <= 2) return launch_v2<PREC, 2>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
-    return launch_v2<PREC, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+    switch (p.nkb) {
+      case 1: return launch_v2<PREC, 1>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+      case 2: return launch_v2<PREC, 2>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+      case 3: return launch_v2<PREC, 3>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+      case 4: return launch_v2<PREC, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+      default: return FAMST_ENOTIMPL;
+    }
   }
 #define DT_CASE(NKB)                                                                        \
   if (p.nkb <= NKB) {                                                                       \
