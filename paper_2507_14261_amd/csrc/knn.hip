@@ -3,6 +3,7 @@
 // direct-difference re-ranking and exact recomputation of rows the
 // screening bound cannot certify.
 #include "famst_common.hpp"
+#include "prims.hpp"
 #include "select.hpp"
 
 namespace famst {
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
-    float tau, float* __restrict__ ubound) {
+    float tau, float* __restrict__ ubound, const int* __restrict__ perm) {
   using S = Scr<PREC>;
   constexpr int QB = 4, KC = 32, QW = 64, BN = 64;
   constexpr int TILE = BN * NKB * 64;   // 64 rows x NKB 64-byte chunks
@@ -526,9 +527,19 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
   // its slot.  Every thread issues NKB + 1 loads per tile (rows past the
   // cloud re-read valid data), which keeps the vmcnt bookkeeping static.
+  // Scan order: with a spatial order (perm != null: rows of Xq are the
+  // points perm[.], grouped by nearest pivot) the scan starts at the tile
+  // holding the block's own queries and wraps around, so each query meets
+  // its likely neighbours first and its threshold tightens early.
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
+  const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
+  auto tile_row = [&](int it) {
+    int ti = it + tstart;
+    ti = ti >= ntile ? ti - ntile : ti;
+    return bd.c0 + ti * BN;
+  };
   auto issue = [&](int it) {
-    const int t0 = bd.c0 + it * BN;
+    const int t0 = tile_row(it % ntile);
     char* stage = smem + (it % PIPE) * STG;
 #pragma unroll
     for (int i = 0; i < NKB; ++i) {
@@ -549,7 +560,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     wait_vmcnt<(PIPE - 2) * (NKB + 1)>();   // this thread's loads of tile it are done
     __builtin_amdgcn_s_barrier();           // ... and every thread's; tile it-1 is consumed
     issue(it + PIPE - 1);                   // into the stage tile it-1 used
-    const int t0 = bd.c0 + it * BN;
+    const int t0 = tile_row(it);
     const char* tile = smem + (it % PIPE) * STG;
     const float* tn = reinterpret_cast<const float*>(tile + TILE);
     // two halves of 32 rows: half the accumulators are live at a time
@@ -630,11 +641,12 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 
   // ---- write the candidate lists and the bound of the rejected elements
+  // (rows and ids back in the caller's numbering under a spatial order)
   if (g == 0) {
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       const int q = wq0 + qb * 16 + i16;
-      if (q < bd.q1) ubound[q] = U[qb] + nqq[qb];
+      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqq[qb];
     }
   }
   const int half = lane >> 5, rel = lane & 31;
@@ -642,9 +654,135 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   for (int L = 0; L < 32; ++L) {
     const int q = wq0 + 2 * L + half;
     if (q < bd.q1) {
-      cand_s[(int64_t)q * KC + rel] = ls[L];
-      cand_j[(int64_t)q * KC + rel] = lj[L];
+      const int qo = perm ? perm[q] : q;
+      const int jv = lj[L];
+      cand_s[(int64_t)qo * KC + rel] = ls[L];
+      cand_j[(int64_t)qo * KC + rel] = (perm && jv != 0x7FFFFFFF) ? perm[jv] : jv;
     }
+  }
+}
+
+// --------------------------------------------- spatial order of the scan
+// Every point (row of the screening copy) is assigned to the nearest of
+// NPIV pivot rows (rows floor(i n / NPIV)) by screened squared distance
+// |p|^2 - 2 x.p, ties to the smaller pivot; sorting by pivot groups nearby
+// points, which only changes the order in which the screening visits rows.
+constexpr int NPIV = 256;
+
+template <int PREC, int NKB>
+__global__ __launch_bounds__(256) void pivot_assign_kernel(const void* __restrict__ Xq_,
+                                                           const float* __restrict__ nq, int n,
+                                                           uint32_t* __restrict__ key,
+                                                           int* __restrict__ idx) {
+  constexpr int QB = 4, RS = NKB * 64, cpr = NKB * 4;
+  constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
+  const char* Xb = reinterpret_cast<const char*>(Xq_);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float* pn = reinterpret_cast<float*>(smem + NPIV * RS);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, i16 = lane & 15;
+  for (int c = tid; c < NPIV * cpr; c += 256) {
+    const int r = c / cpr, sc = c - r * cpr;
+    const int64_t prow = (int64_t)r * n / NPIV;
+    *reinterpret_cast<i32x4*>(smem + r * RS + ((sc ^ (r & smask)) << 4)) =
+        *reinterpret_cast<const i32x4*>(Xb + prow * RS + sc * 16);
+  }
+  for (int r = tid; r < NPIV; r += 256) pn[r] = nq[(int64_t)r * n / NPIV];
+  __syncthreads();
+  const int wq0 = blockIdx.x * 256 + wave * 64;
+  i32x4 qf[QB][NKB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = wq0 + qb * 16 + i16;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+      qf[qb][kb] = q < n ? *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16)
+                         : i32x4{0, 0, 0, 0};
+  }
+  float best[QB];
+  int bi[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    best[qb] = F_INF;
+    bi[qb] = 0;
+  }
+  for (int pt = 0; pt < NPIV / 64; ++pt) {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      f32x4 acc[QB];
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) acc[qb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const int r = pt * 64 + jb * 16 + i16;
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        const int cc = kb * 4 + g;
+        const i32x4 a = *reinterpret_cast<const i32x4*>(smem + r * RS + ((cc ^ (r & smask)) << 4));
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          if constexpr (PREC == FAMST_FP32) {
+            const f32x4 af = __builtin_bit_cast(f32x4, a);
+            const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb], 0, 0, 0);
+            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb], 0, 0, 0);
+            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb], 0, 0, 0);
+            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb], 0, 0, 0);
+          } else {
+            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb], 0, 0, 0);
+          }
+        }
+      }
+      // lane holds pivots pt*64 + jb*16 + 4g + rr for its query qb*16 + i16
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int pi = pt * 64 + jb * 16 + 4 * g + rr;
+          const float v = __builtin_fmaf(-2.f, acc[qb][rr], pn[pi]);
+          if (v < best[qb]) {   // pivots are visited in ascending order per lane
+            best[qb] = v;
+            bi[qb] = pi;
+          }
+        }
+    }
+  }
+  // combine the four lane groups of each query (smaller value, then smaller pivot)
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      const float ov = __shfl_xor(best[qb], o);
+      const int oi = __shfl_xor(bi[qb], o);
+      if (ov < best[qb] || (ov == best[qb] && oi < bi[qb])) {
+        best[qb] = ov;
+        bi[qb] = oi;
+      }
+    }
+    const int q = wq0 + qb * 16 + i16;
+    if (g == 0 && q < n) {
+      key[q] = (uint32_t)bi[qb];
+      idx[q] = q;
+    }
+  }
+}
+
+// Permuted copies of the screening rows, norms and rounding norms.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const char* __restrict__ Xq, int RS,
+                                                          const float* __restrict__ nq,
+                                                          const float* __restrict__ qerr,
+                                                          const int* __restrict__ perm, int64_t n,
+                                                          char* __restrict__ Xp, float* __restrict__ nqp,
+                                                          float* __restrict__ qerrp) {
+  const int cpr = RS / 16;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n * cpr) return;
+  const int64_t q = c / cpr;
+  const int sc = (int)(c - q * cpr);
+  const int src = perm[q];
+  *reinterpret_cast<i32x4*>(Xp + q * RS + sc * 16) =
+      *reinterpret_cast<const i32x4*>(Xq + (int64_t)src * RS + sc * 16);
+  if (sc == 0) {
+    nqp[q] = nq[src];
+    qerrp[q] = qerr[src];
   }
 }
 
@@ -1146,6 +1284,7 @@ struct BandArgs {
   const unsigned* gstat;
   float arith_c, tau;
   float* ubound;
+  const int* perm;   // spatial order of the rows of Xq (null: identity)
 };
 
 template <int PREC, int NKB>
@@ -1159,7 +1298,7 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
-                ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
+                ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);
 }
 
 template <int PREC>
@@ -1185,6 +1324,49 @@ static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq
   DT_CASE(8)
 #undef DT_CASE
   return FAMST_ENOTIMPL;
+}
+
+template <int PREC, int NKB>
+static int launch_pivots(int64_t n, hipStream_t s, const void* Xq, const float* nq, uint32_t* key,
+                         int* idx) {
+  auto kern = pivot_assign_kernel<PREC, NKB>;
+  const size_t lds = (size_t)NPIV * NKB * 64 + NPIV * 4;
+  static bool attr = false;
+  if (!attr) {
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  return launch("pivots", kern, dim3(cdiv(n, 256)), dim3(256), lds, s, Xq, nq, (int)n, key, idx);
+}
+
+template <int PREC>
+static int pivots_prec(int nkb, int64_t n, hipStream_t s, const void* Xq, const float* nq,
+                       uint32_t* key, int* idx) {
+  switch (nkb) {
+    case 1: return launch_pivots<PREC, 1>(n, s, Xq, nq, key, idx);
+    case 2: return launch_pivots<PREC, 2>(n, s, Xq, nq, key, idx);
+    case 3: return launch_pivots<PREC, 3>(n, s, Xq, nq, key, idx);
+    case 4: return launch_pivots<PREC, 4>(n, s, Xq, nq, key, idx);
+    default: return FAMST_ENOTIMPL;
+  }
+}
+
+static int dispatch_pivots(int prec, int nkb, int64_t n, hipStream_t s, const void* Xq,
+                           const float* nq, uint32_t* key, int* idx) {
+  return prec == FAMST_FP32 ? pivots_prec<FAMST_FP32>(nkb, n, s, Xq, nq, key, idx)
+                            : pivots_prec<FAMST_BF16>(nkb, n, s, Xq, nq, key, idx);
+}
+
+// Nearest-pivot assignment, stable sort by pivot, permuted screening copy.
+static int spatial_order(int prec, int nkb, int64_t n, hipStream_t s, const void* Xq, const float* nq,
+                         const float* qerr, uint32_t* key, uint32_t* key2, int* idx, int* perm,
+                         void* tmp, size_t tmpb, char* Xp, float* nqp, float* qerrp) {
+  FAMST_TRY(dispatch_pivots(prec, nkb, n, s, Xq, nq, key, idx));
+  FAMST_TRY(sort_pairs_u32_i32(tmp, tmpb, key, key2, idx, perm, (size_t)n, 8, s));
+  const int RS = nkb * 64;
+  return launch("gather_rows", gather_rows_kernel, dim3(cdiv(n * (RS / 16), 256)), dim3(256), 0, s,
+                reinterpret_cast<const char*>(Xq), RS, nq, qerr, perm, n, Xp, nqp, qerrp);
 }
 
 }  // namespace famst
@@ -1231,6 +1413,18 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   int* bad = cv.take<int>(n);
   unsigned long long* ctr = cv.take<unsigned long long>(4);
   int* ovf = cv.take<int>(1);
+  // spatial order of the scan (one large cloud, pipelined screening)
+  const bool spatial = p.piped && B == 1 && n >= 32768;
+  const size_t sn = spatial ? (size_t)n : 0;
+  char* Xp = cv.take<char>(sn * p.DP * esz);
+  float* nqp = cv.take<float>(sn);
+  float* qerrp = cv.take<float>(sn);
+  uint32_t* pkey = cv.take<uint32_t>(sn);
+  uint32_t* pkey2 = cv.take<uint32_t>(sn);
+  int* pidx = cv.take<int>(sn);
+  int* perm = cv.take<int>(sn);
+  const size_t ptmpb = spatial ? sort_pairs_u32_i32_bytes(sn) : 0;
+  void* ptmp = cv.take<char>(ptmpb);
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
@@ -1271,13 +1465,23 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
 
   // matrix-core dot products and norms: |err| <= (2d + 8) 2^-24 (|x|^2 + |y|^2)
   const float arith_c = (float)(2 * p.DP + 8) * 5.9604645e-8f;
-  const BandArgs ba{k, qerr, gstat, arith_c, tau32(d), ub};
+  BandArgs ba{k, qerr, gstat, arith_c, tau32(d), ub, nullptr};
+  const void* Xs = Xq;
+  const float* nqs = nq;
+  if (spatial) {
+    FAMST_TRY(spatial_order(prec, p.nkb, n, s, Xq, nq, qerr, pkey, pkey2, pidx, perm, ptmp, ptmpb, Xp,
+                            nqp, qerrp));
+    Xs = Xp;
+    nqs = nqp;
+    ba.qerr = qerrp;
+    ba.perm = perm;
+  }
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
   else if (prec == FAMST_FP32)
-    FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
+    FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
   else
-    FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
+    FAMST_TRY(dispatch_dt<FAMST_BF16>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
 
   RerankArgs ra;
   ra.X = X; ra.n = n; ra.d = d; ra.offs = offs_d; ra.B = B; ra.k = k; ra.KC = p.KC;
