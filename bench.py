@@ -96,7 +96,7 @@ def time_path(F, torch, Xd, k, lam, seed, rounds, precision, exact, steps, warmu
     phases = {}
     if profile:
         F.profile_enable(False)
-        for name in ["prep", "dist_topk", "rerank", "exact_row", "sort", "scan", "graph_keys",
+        for name in ["prep", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan", "graph_keys",
                      "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
                      "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]:
             nl, ms = F.profile_read(name)

@@ -667,7 +667,12 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 // NPIV pivot rows (rows floor(i n / NPIV)) by screened squared distance
 // |p|^2 - 2 x.p, ties to the smaller pivot; sorting by pivot groups nearby
 // points, which only changes the order in which the screening visits rows.
-constexpr int NPIV = 256;
+// The pivots pass through LDS in chunks of 256.
+#ifndef FAMST_NPIV
+#define FAMST_NPIV 1024
+#endif
+constexpr int NPIV = FAMST_NPIV, PCH = 256;
+constexpr int NPIV_BITS = NPIV <= 256 ? 8 : (NPIV <= 1024 ? 10 : (NPIV <= 4096 ? 12 : 16));
 
 template <int PREC, int NKB>
 __global__ __launch_bounds__(256) void pivot_assign_kernel(const void* __restrict__ Xq_,
@@ -678,16 +683,8 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const void* __restric
   constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  float* pn = reinterpret_cast<float*>(smem + NPIV * RS);
+  float* pn = reinterpret_cast<float*>(smem + PCH * RS);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, i16 = lane & 15;
-  for (int c = tid; c < NPIV * cpr; c += 256) {
-    const int r = c / cpr, sc = c - r * cpr;
-    const int64_t prow = (int64_t)r * n / NPIV;
-    *reinterpret_cast<i32x4*>(smem + r * RS + ((sc ^ (r & smask)) << 4)) =
-        *reinterpret_cast<const i32x4*>(Xb + prow * RS + sc * 16);
-  }
-  for (int r = tid; r < NPIV; r += 256) pn[r] = nq[(int64_t)r * n / NPIV];
-  __syncthreads();
   const int wq0 = blockIdx.x * 256 + wave * 64;
   i32x4 qf[QB][NKB];
 #pragma unroll
@@ -705,44 +702,55 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const void* __restric
     best[qb] = F_INF;
     bi[qb] = 0;
   }
-  for (int pt = 0; pt < NPIV / 64; ++pt) {
+  for (int p0 = 0; p0 < NPIV; p0 += PCH) {
+    __syncthreads();   // the previous chunk is consumed
+    for (int c = tid; c < PCH * cpr; c += 256) {
+      const int r = c / cpr, sc = c - r * cpr;
+      const int64_t prow = (int64_t)(p0 + r) * n / NPIV;
+      *reinterpret_cast<i32x4*>(smem + r * RS + ((sc ^ (r & smask)) << 4)) =
+          *reinterpret_cast<const i32x4*>(Xb + prow * RS + sc * 16);
+    }
+    for (int r = tid; r < PCH; r += 256) pn[r] = nq[(int64_t)(p0 + r) * n / NPIV];
+    __syncthreads();
+    for (int pt = 0; pt < PCH / 64; ++pt) {
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      f32x4 acc[QB];
+      for (int jb = 0; jb < 4; ++jb) {
+        f32x4 acc[QB];
 #pragma unroll
-      for (int qb = 0; qb < QB; ++qb) acc[qb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      const int r = pt * 64 + jb * 16 + i16;
+        for (int qb = 0; qb < QB; ++qb) acc[qb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int r = pt * 64 + jb * 16 + i16;
 #pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        const int cc = kb * 4 + g;
-        const i32x4 a = *reinterpret_cast<const i32x4*>(smem + r * RS + ((cc ^ (r & smask)) << 4));
+        for (int kb = 0; kb < NKB; ++kb) {
+          const int cc = kb * 4 + g;
+          const i32x4 a = *reinterpret_cast<const i32x4*>(smem + r * RS + ((cc ^ (r & smask)) << 4));
 #pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-          if constexpr (PREC == FAMST_FP32) {
-            const f32x4 af = __builtin_bit_cast(f32x4, a);
-            const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
-            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb], 0, 0, 0);
-            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb], 0, 0, 0);
-            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb], 0, 0, 0);
-            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb], 0, 0, 0);
-          } else {
-            acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb], 0, 0, 0);
+          for (int qb = 0; qb < QB; ++qb) {
+            if constexpr (PREC == FAMST_FP32) {
+              const f32x4 af = __builtin_bit_cast(f32x4, a);
+              const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+              acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb], 0, 0, 0);
+              acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb], 0, 0, 0);
+              acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb], 0, 0, 0);
+              acc[qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb], 0, 0, 0);
+            } else {
+              acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb], 0, 0, 0);
+            }
           }
         }
+        // lane holds pivots p0 + pt*64 + jb*16 + 4g + rr for its query qb*16 + i16
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int pl = pt * 64 + jb * 16 + 4 * g + rr;
+            const float v = __builtin_fmaf(-2.f, acc[qb][rr], pn[pl]);
+            if (v < best[qb]) {   // pivots are visited in ascending order per lane
+              best[qb] = v;
+              bi[qb] = p0 + pl;
+            }
+          }
       }
-      // lane holds pivots pt*64 + jb*16 + 4g + rr for its query qb*16 + i16
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int pi = pt * 64 + jb * 16 + 4 * g + rr;
-          const float v = __builtin_fmaf(-2.f, acc[qb][rr], pn[pi]);
-          if (v < best[qb]) {   // pivots are visited in ascending order per lane
-            best[qb] = v;
-            bi[qb] = pi;
-          }
-        }
     }
   }
   // combine the four lane groups of each query (smaller value, then smaller pivot)
@@ -1330,7 +1338,7 @@ template <int PREC, int NKB>
 static int launch_pivots(int64_t n, hipStream_t s, const void* Xq, const float* nq, uint32_t* key,
                          int* idx) {
   auto kern = pivot_assign_kernel<PREC, NKB>;
-  const size_t lds = (size_t)NPIV * NKB * 64 + NPIV * 4;
+  const size_t lds = (size_t)PCH * NKB * 64 + PCH * 4;
   static bool attr = false;
   if (!attr) {
     FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -1363,7 +1371,7 @@ static int spatial_order(int prec, int nkb, int64_t n, hipStream_t s, const void
                          const float* qerr, uint32_t* key, uint32_t* key2, int* idx, int* perm,
                          void* tmp, size_t tmpb, char* Xp, float* nqp, float* qerrp) {
   FAMST_TRY(dispatch_pivots(prec, nkb, n, s, Xq, nq, key, idx));
-  FAMST_TRY(sort_pairs_u32_i32(tmp, tmpb, key, key2, idx, perm, (size_t)n, 8, s));
+  FAMST_TRY(sort_pairs_u32_i32(tmp, tmpb, key, key2, idx, perm, (size_t)n, NPIV_BITS, s));
   const int RS = nkb * 64;
   return launch("gather_rows", gather_rows_kernel, dim3(cdiv(n * (RS / 16), 256)), dim3(256), 0, s,
                 reinterpret_cast<const char*>(Xq), RS, nq, qerr, perm, n, Xp, nqp, qerrp);
