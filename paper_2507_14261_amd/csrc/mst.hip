@@ -203,12 +203,23 @@ __global__ __launch_bounds__(256) void tree_weight_kernel(const float* __restric
   __shared__ float ss[256], ee[256];
   const int b = blockIdx.x, t = threadIdx.x;
   const int64_t e0 = offs[b] - b, e1 = offs[b + 1] - b - 1;
+  // thread t adds elements t, t + 256, t + 512, ... in that order; sixteen
+  // loads are issued ahead of the (dependent) compensated additions
   float s = 0.f, c = 0.f;
-  for (int64_t i = e0 + t; i < e1; i += 256) {
-    float x = tw[i], ns, err;
-    two_sum(s, x, ns, err);
-    s = ns;
-    c += err;
+  constexpr int U = 16;
+  for (int64_t i0 = e0 + t; i0 < e1; i0 += 256 * U) {
+    float x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = i0 + 256 * u < e1 ? tw[i0 + 256 * u] : 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + 256 * u < e1) {
+        float ns, err;
+        two_sum(s, x[u], ns, err);
+        s = ns;
+        c += err;
+      }
+    }
   }
   ss[t] = s;
   ee[t] = c;

@@ -35,24 +35,37 @@ __device__ __forceinline__ Best best_merge(Best a, Best b) {
   return r;
 }
 
+// One block of RNT threads per edge: sixteen 16-lane groups measure
+// neighbours in parallel; per-wave results meet in LDS.
+constexpr int RNT = 256, RNW = RNT / 64;
+
+struct RefineSmem {
+  float s1[RNW], s2[RNW];
+  int id1[RNW];
+  double v64[RNW];
+  int i64[RNW];
+};
+
 // Smallest (s(x, anchor), x) over neighbours x of `row` in component `c`
-// with x != excl; evaluated by the whole wave, four 16-lane groups at a
-// time.  Near-ties with the runner-up are settled in float64.
+// with x != excl; evaluated by the whole block, sixteen 16-lane groups at a
+// time.  Near-ties with the runner-up are settled in float64.  Every
+// thread of the block returns the same result.
 __device__ Best row_argmin(const float* __restrict__ X, int d, const int64_t* __restrict__ row_ptr,
                            const int32_t* __restrict__ col, const int32_t* __restrict__ comp,
                            int row, int c, int excl, int anchor, float tau, bool* used64,
-                           double* best64) {
-  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+                           double* best64, RefineSmem& sm) {
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15, lane = t & 63, wave = t >> 6;
+  constexpr int NG = RNT / 16;
   const int64_t p0 = row_ptr[row], p1 = row_ptr[row + 1];
   const float* xa = X + (int64_t)anchor * d;
   Best b{F_INF, 0x7FFFFFFF, F_INF};
-  for (int64_t p = p0 + grp; p < p1; p += 4) {
+  for (int64_t p = p0 + grp; p < p1; p += NG) {
     int x = col[p];
     if (comp[x] != c || x == excl) continue;   // uniform within the group
     float s = sq32_group(X + (int64_t)x * d, xa, d, r16);
     best_push(b, s, x);
   }
-  // combine the four groups (lanes 0, 16, 32, 48 hold identical copies per group)
+  // combine the groups: the four of a wave by shuffles, the waves in LDS
 #pragma unroll
   for (int o = 16; o <= 32; o <<= 1) {
     Best other;
@@ -61,6 +74,16 @@ __device__ Best row_argmin(const float* __restrict__ X, int d, const int64_t* __
     other.s2 = __shfl_xor(b.s2, o);
     b = best_merge(b, other);
   }
+  if (lane == 0) {
+    sm.s1[wave] = b.s1;
+    sm.id1[wave] = b.id1;
+    sm.s2[wave] = b.s2;
+  }
+  __syncthreads();
+  b = Best{sm.s1[0], sm.id1[0], sm.s2[0]};
+#pragma unroll
+  for (int w = 1; w < RNW; ++w) b = best_merge(b, Best{sm.s1[w], sm.id1[w], sm.s2[w]});
+  __syncthreads();   // the slots are reused below / by the next call
   *used64 = false;
   const float up = 1.0f + 2.0f * tau, dn = 1.0f - 2.0f * tau;
   if (b.s1 < F_INF && b.s2 * dn <= b.s1 * up) {
@@ -68,7 +91,7 @@ __device__ Best row_argmin(const float* __restrict__ X, int d, const int64_t* __
     *used64 = true;
     double m64 = __builtin_inf();
     int mid = 0x7FFFFFFF;
-    for (int64_t p = p0 + grp; p < p1; p += 4) {
+    for (int64_t p = p0 + grp; p < p1; p += NG) {
       int x = col[p];
       if (comp[x] != c || x == excl) continue;
       float s = sq32_group(X + (int64_t)x * d, xa, d, r16);
@@ -89,7 +112,21 @@ __device__ Best row_argmin(const float* __restrict__ X, int d, const int64_t* __
         mid = oi;
       }
     }
-    // the winner's float32 value (all groups agree on mid)
+    if (lane == 0) {
+      sm.v64[wave] = m64;
+      sm.i64[wave] = mid;
+    }
+    __syncthreads();
+    m64 = sm.v64[0];
+    mid = sm.i64[0];
+#pragma unroll
+    for (int w = 1; w < RNW; ++w)
+      if (key_less64(sm.v64[w], sm.i64[w], m64, mid)) {
+        m64 = sm.v64[w];
+        mid = sm.i64[w];
+      }
+    __syncthreads();
+    // the winner's float32 value (every group computes it)
     b.id1 = mid;
     b.s1 = sq32_group(X + (int64_t)mid * d, xa, d, r16);
     *best64 = m64;
@@ -109,7 +146,7 @@ __device__ bool strictly_less(float sc, float si, const float* ca, const float* 
   return vc < vi;
 }
 
-__global__ __launch_bounds__(64) void refine_kernel(const float* __restrict__ X, int d,
+__global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X, int d,
                                                     const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col,
                                                     const int32_t* __restrict__ comp,
@@ -118,6 +155,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const float* __restrict__ X,
                                                     const int32_t* __restrict__ ea,
                                                     const int32_t* __restrict__ eb, int64_t ne,
                                                     unsigned long long* __restrict__ delta) {
+  __shared__ RefineSmem sm;
   const int64_t e = blockIdx.x;
   if (e >= ne) return;
   const int r16 = threadIdx.x & 15;
@@ -130,7 +168,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const float* __restrict__ X,
   // u side: neighbours of u in C_a, measured to v
   bool u64;
   double b64 = 0.0;
-  Best bu = row_argmin(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64);
+  Best bu = row_argmin(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64, sm);
   if (bu.s1 < F_INF &&
       strictly_less(bu.s1, ds, X + (int64_t)bu.id1 * d, xv, xu, xv, d, tau, u64, b64)) {
     us = bu.id1;
@@ -138,7 +176,7 @@ __global__ __launch_bounds__(64) void refine_kernel(const float* __restrict__ X,
   }
   // v side: neighbours of v in C_b (excluding the original u), measured to u*
   const float* xus = X + (int64_t)us * d;
-  Best bv = row_argmin(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64);
+  Best bv = row_argmin(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64, sm);
   if (bv.s1 < F_INF &&
       strictly_less(bv.s1, ds, xus, X + (int64_t)bv.id1 * d, xus, X + (int64_t)vs * d, d, tau, u64,
                     b64)) {
@@ -179,7 +217,7 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   unsigned long long last = 0;
   while (r < max_rounds) {
     FAMST_HIP(hipMemsetAsync(dc, 0, sizeof(unsigned long long), s));
-    FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(64), 0, s, X, d, row_ptr,
+    FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr,
                      col, comp, eu, ev, ew, ea, eb, n_edges, dc));
     FAMST_HIP(hipMemcpyAsync(&last, dc, sizeof(last), hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipStreamSynchronize(s));
