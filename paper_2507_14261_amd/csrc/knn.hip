@@ -528,14 +528,26 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   // its slot.  Every thread issues NKB + 1 loads per tile (rows past the
   // cloud re-read valid data), which keeps the vmcnt bookkeeping static.
   // Scan order: with a spatial order (perm != null: rows of Xq are the
-  // points perm[.], grouped by nearest pivot) the scan starts at the tile
-  // holding the block's own queries and wraps around, so each query meets
-  // its likely neighbours first and its threshold tightens early.
+  // points perm[.], grouped by nearest pivot) the scan first visits the
+  // TOWN tiles from the one holding the block's own queries (their likely
+  // neighbours: the thresholds tighten early), then every other tile in
+  // ascending order, so that the blocks resident at one time stream the
+  // same tiles through L2.
+  constexpr int TOWN = 16;
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
+  const int town = perm ? min(TOWN, ntile) : 0;
   const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
+  const int tend = tstart + town;   // own tiles: [tstart, tend) modulo ntile
   auto tile_row = [&](int it) {
-    int ti = it + tstart;
-    ti = ti >= ntile ? ti - ntile : ti;
+    int ti;
+    if (it < town) {
+      ti = tstart + it;
+      ti = ti >= ntile ? ti - ntile : ti;
+    } else {
+      const int r = it - town;
+      if (tend <= ntile) ti = r < tstart ? r : r + town;
+      else ti = (tend - ntile) + r;
+    }
     return bd.c0 + ti * BN;
   };
   auto issue = [&](int it) {
