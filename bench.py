@@ -66,6 +66,11 @@ WORKLOADS = {
 }
 
 
+PHASES = ["prep", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan",
+          "graph_keys", "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
+          "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -96,9 +101,7 @@ def time_path(F, torch, Xd, k, lam, seed, rounds, precision, exact, steps, warmu
     phases = {}
     if profile:
         F.profile_enable(False)
-        for name in ["prep", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan", "graph_keys",
-                     "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
-                     "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]:
+        for name in PHASES:
             nl, ms = F.profile_read(name)
             if nl:
                 phases[name] = {"launches": nl, "total_ms": round(ms, 3)}
@@ -141,7 +144,11 @@ def bench_clouds(args, F, torch):
         F.profile_enable(False)
         nl, ms = F.profile_read(kern)
         res[name] = {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "kernel": kern,
-                     "kernel_avg_ms": ms / nl if nl else None}
+                     "kernel_avg_ms": ms / nl if nl else None, "phases": {}}
+        for ph in PHASES:
+            pl, pms = F.profile_read(ph)
+            if pl:
+                res[name]["phases"][ph] = round(pms / args.steps, 3)
     # exact path: every Prim step streams the rows still outside the tree, so
     # one launch reads sum_i n_i (n_i - 1) / 2 rows of d float32 values
     sizes = np.diff(offs).astype(np.float64)
@@ -163,7 +170,8 @@ def bench_clouds(args, F, torch):
                      "avg_ms": round(ex["kernel_avg_ms"], 3) if ex["kernel_avg_ms"] else None,
                      "algorithmic_GB": round(prim_bytes / 1e9, 3)},
         "k16_path": {"ms_per_step": round(res["k16"]["ms_per_step"], 3),
-                     "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1)},
+                     "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1),
+                     "phases_ms_per_step": res["k16"]["phases"]},
         "cpu_baseline": None,
     }
 

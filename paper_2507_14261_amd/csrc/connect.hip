@@ -1,6 +1,7 @@
 // Phase 2 of FAMST: the undirected graph G of the neighbour lists and its
 // connected components (Alg. 2), then lambda random inter-component edges
 // per component pair (Alg. 3).
+#include <numeric>
 #include <vector>
 
 #include "famst_common.hpp"
@@ -69,10 +70,14 @@ __device__ __forceinline__ int uf_find(int* parent, int x) {
   }
 }
 
-__global__ void uf_hook_kernel(const int32_t* __restrict__ nbr, int64_t n, int k,
+// Thread t takes edge (t * stride) mod (n k), a bijection for a stride
+// coprime to n k: concurrent threads then work on unrelated vertices, not
+// on neighbouring entries of parent[] (atomics on one cache line serialise).
+__global__ void uf_hook_kernel(const int32_t* __restrict__ nbr, int64_t n, int k, uint64_t stride,
                                int* __restrict__ parent) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * k) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  const int64_t e = (int64_t)(((unsigned __int128)t * stride) % (unsigned __int128)(n * k));
   int a = (int)(e / k), b = nbr[e];
   if (b < 0 || b >= n) return;
   while (true) {
@@ -269,8 +274,10 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, rowcnt, row_ptr, n + 1, s));
   // ---- components
   FAMST_TRY(iota_i32(parent, n, s));
+  uint64_t stride = 1000003;   // odd, coprime to n k (checked)
+  while (std::gcd(stride, (uint64_t)(n * k)) != 1) stride += 2;
   FAMST_TRY(launch("uf_hook", uf_hook_kernel, dim3(cdiv(n * k, 256)), dim3(256), 0, s, nbr, n, k,
-                   parent));
+                   stride % (uint64_t)(n * k), parent));
   FAMST_TRY(launch("uf_roots", uf_roots_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, parent, n,
                    isroot));
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, isroot, lab, n + 1, s));
