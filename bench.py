@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--fp32-steps", type=int, default=1)
-    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true", help="time only the bf16-screened path")
     ap.add_argument("--calib-copy", action="store_true",

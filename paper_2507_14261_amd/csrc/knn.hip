@@ -376,12 +376,25 @@ typedef int i32x32 __attribute__((ext_vector_type(32)));
 typedef __attribute__((address_space(1))) const void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
 constexpr int PIPE = 4;
+static_assert((PIPE & (PIPE - 1)) == 0, "stage index by mask");
 
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   // gfx9 s_waitcnt: vmcnt in bits [3:0] and [15:14]; expcnt and lgkmcnt at
   // their maxima (not waited for)
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// 8-byte LDS read that waits for its own result inside the asm statement.
+// Ordinary LDS reads placed after direct global->LDS loads make the compiler
+// wait for every load in flight (it cannot tell which LDS bytes they
+// write); the band constants read here are never written by those loads.
+__device__ __forceinline__ float2 lds_read_f2(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  f2v v;
+  const unsigned a = (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float2*)p;
+  asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
+  return float2{v.x, v.y};
 }
 
 // Screening band above the k-th screened value T of a query: wide enough
@@ -420,8 +433,8 @@ struct Band {
 // the new k-th entry).
 template <int QB, int NE, class SpFn>
 __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbmask, float (&U)[QB],
-                                            const float (&nqq)[QB], const float (&bc0)[QB],
-                                            const float (&bc1)[QB], const Band& band, int kk,
+                                            const float (&nqq)[QB], const float2* bcw,
+                                            const Band& band, int kk,
                                             SpFn spf, int t0, int c1, int wq0, int lane, int g,
                                             int i16) {
   const int half = lane >> 5, rel = lane & 31;
@@ -466,10 +479,32 @@ __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbm
         ls[L] = ns;
         lj[L] = nj;
         const float Tk = readlane_f(ns, 32 * h + kk - 1);
-        const float Un = (Tk - nqv) + band(Tk, readlane_f(bc0[qb], src), readlane_f(bc1[qb], src));
+        const float2 bcv = lds_read_f2(bcw + qb * 16 + (src & 15));
+        const float Un = (Tk - nqv) + band(Tk, bcv.x, bcv.y);
         U[qb] = (i16 == (src & 15)) ? Un : U[qb];
       }
     }
+  }
+}
+
+// A query fragment (8 bf16 or 4 float32 values) times -2; exact for every
+// finite input (a power-of-two scaling, far from overflow for rows that
+// passed the norm check).
+template <int PREC>
+__device__ __forceinline__ i32x4 neg2_fragment(i32x4 v) {
+  if constexpr (PREC == FAMST_FP32) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = __float_as_int(-2.f * __int_as_float(v[i]));
+    return v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned u = (unsigned)v[i];
+      const unsigned lo = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u & 0xFFFFu)));
+      const unsigned hi = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u >> 16)));
+      v[i] = (int)(lo | (hi << 16));
+    }
+    return v;
   }
 }
 
@@ -496,22 +531,28 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   constexpr int RS = NKB * 64, cpr = NKB * 4;
   constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
 
-  // resident query fragments
+  // resident query fragments, scaled by -2 (exact): the products then
+  // accumulate onto the row norms and yield the screened value
+  // |y|^2 - 2 x.y directly.  The band constants of the wave's 64 queries
+  // sit in LDS after the stages (only insertions read them).
   i32x4 qf[QB][NKB];
-  float nqq[QB], bc0[QB], bc1[QB], U[QB];
+  float nqq[QB], U[QB];
   const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
+  float2* bcw = reinterpret_cast<float2*>(smem + PIPE * STG) + wave * QW;
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int q = wq0 + qb * 16 + i16;
     const bool ok = q < bd.q1;
     nqq[qb] = ok ? nq[q] : 0.f;
-    band.consts(nqq[qb], ok ? qerr[q] : 0.f, bc0[qb], bc1[qb]);
+    float c0, c1;
+    band.consts(nqq[qb], ok ? qerr[q] : 0.f, c0, c1);
+    if (g == 0) bcw[qb * 16 + i16] = float2{c0, c1};
     U[qb] = ok ? F_INF : -F_INF;
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
       i32x4 v = {0, 0, 0, 0};
       if (ok) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
-      qf[qb][kb] = v;
+      qf[qb][kb] = neg2_fragment<PREC>(v);
     }
   }
   f32x32 ls;
@@ -522,37 +563,23 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     lj[L] = 0x7FFFFFFF;
   }
 
-  // Loads of tile `it` into stage it % PIPE: chunk slot p of the stage holds
-  // chunk (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
+  // Loads of a tile into a stage: chunk slot p of the stage holds chunk
+  // (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
   // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
   // its slot.  Every thread issues NKB + 1 loads per tile (rows past the
   // cloud re-read valid data), which keeps the vmcnt bookkeeping static.
-  // Scan order: with a spatial order (perm != null: rows of Xq are the
-  // points perm[.], grouped by nearest pivot) the scan first visits the
-  // TOWN tiles from the one holding the block's own queries (their likely
-  // neighbours: the thresholds tighten early), then every other tile in
-  // ascending order, so that the blocks resident at one time stream the
-  // same tiles through L2.
-  constexpr int TOWN = 16;
+  // Scan order: tiles tstart, tstart + 1, ... cyclically.  With a spatial
+  // order (perm != null: rows of Xq are the points perm[.], grouped by
+  // nearest pivot) tstart is the tile of the block's own first query, so the
+  // likely neighbours come first and the thresholds tighten early.  Two
+  // scalar counters follow the tile to load and the tile to compute.
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
-  const int town = perm ? min(TOWN, ntile) : 0;
   const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
-  const int tend = tstart + town;   // own tiles: [tstart, tend) modulo ntile
-  auto tile_row = [&](int it) {
-    int ti;
-    if (it < town) {
-      ti = tstart + it;
-      ti = ti >= ntile ? ti - ntile : ti;
-    } else {
-      const int r = it - town;
-      if (tend <= ntile) ti = r < tstart ? r : r + town;
-      else ti = (tend - ntile) + r;
-    }
-    return bd.c0 + ti * BN;
-  };
-  auto issue = [&](int it) {
-    const int t0 = tile_row(it % ntile);
-    char* stage = smem + (it % PIPE) * STG;
+  int tl = tstart;   // next tile to load
+  auto issue = [&](int stg) {
+    const int t0 = bd.c0 + tl * BN;
+    tl = tl + 1 == ntile ? 0 : tl + 1;
+    char* stage = smem + stg * STG;
 #pragma unroll
     for (int i = 0; i < NKB; ++i) {
       const int p = tid + 256 * i;
@@ -565,90 +592,99 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     const int row = min(t0 + lane, bd.c1 - 1);
     __builtin_amdgcn_global_load_lds((gptr_t)(nq + row), (lptr_t)(stage + TILE), 4, 0, 0);
   };
-#pragma unroll
-  for (int it = 0; it < PIPE - 1; ++it) issue(it);
-
-  for (int it = 0; it < ntile; ++it) {
+  // one tile consumed by every thread: wait for the next tile's loads, let
+  // every wave pass, and refill the stage the consumed tile used
+  auto next_tile = [&](int it) {
     wait_vmcnt<(PIPE - 2) * (NKB + 1)>();   // this thread's loads of tile it are done
     __builtin_amdgcn_s_barrier();           // ... and every thread's; tile it-1 is consumed
-    issue(it + PIPE - 1);                   // into the stage tile it-1 used
-    const int t0 = tile_row(it);
-    const char* tile = smem + (it % PIPE) * STG;
+    issue((it + PIPE - 1) & (PIPE - 1));    // into the stage tile it-1 used
+  };
+
+  // Products of one half (32 rows) of a tile: the accumulators start at the
+  // norms of their rows; A fragments double-buffered (the LDS reads of
+  // K-step kb + 1 are issued before the products of K-step kb).
+  auto products = [&](const char* tile, int jh, f32x4 (&acc)[QB][2]) {
     const float* tn = reinterpret_cast<const float*>(tile + TILE);
-    // two halves of 32 rows: half the accumulators are live at a time
 #pragma unroll
-    for (int jh = 0; jh < 2; ++jh) {
-      float nqj[2][4];
+    for (int jj = 0; jj < 2; ++jj) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * jh + jj) * 16 + 4 * g);
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) acc[qb][jj] = v;
+    }
+    auto lda = [&](int kb, i32x4 (&a)[2]) {
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * jh + jj) * 16 + 4 * g);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
+        const int r = (2 * jh + jj) * 16 + i16;
+        const int cc = kb * 4 + g;
+        a[jj] = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
       }
-      f32x4 acc[QB][2];
+    };
+    i32x4 acur[2], anxt[2];
+    lda(0, acur);
 #pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb + 1 < NKB) lda(kb + 1, anxt);
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) acc[qb][jj] = f32x4{0.f, 0.f, 0.f, 0.f};
-      // A fragments double-buffered: the LDS reads of K-step kb + 1 are issued
-      // before the matrix-core products of K-step kb
-      auto lda = [&](int kb, i32x4 (&a)[2]) {
+      for (int jj = 0; jj < 2; ++jj) {
+        const i32x4 a = acur[jj];
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const int r = (2 * jh + jj) * 16 + i16;
-          const int cc = kb * 4 + g;
-          a[jj] = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
-        }
-      };
-      i32x4 acur[2], anxt[2];
-      lda(0, acur);
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        {
-          if (kb + 1 < NKB) lda(kb + 1, anxt);
-#pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
-            const i32x4 a = acur[jj];
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-              if constexpr (PREC == FAMST_FP32) {
-                const f32x4 af = __builtin_bit_cast(f32x4, a);
-                const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
-                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jj], 0, 0, 0);
-                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jj], 0, 0, 0);
-                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jj], 0, 0, 0);
-                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jj], 0, 0, 0);
-              } else {
-                acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
-              }
-            }
-          }
-          if (kb + 1 < NKB) {
-            acur[0] = anxt[0];
-            acur[1] = anxt[1];
+        for (int qb = 0; qb < QB; ++qb) {
+          if constexpr (PREC == FAMST_FP32) {
+            const f32x4 af = __builtin_bit_cast(f32x4, a);
+            const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jj], 0, 0, 0);
+          } else {
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
           }
         }
       }
-      // screening filter: lane holds rows t0h + jj*16 + 4g + r, query qb*16 + i16
-      const int t0h = t0 + 32 * jh;
-      unsigned qbmask = 0;
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        float m = F_INF;
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) m = fminf(m, __builtin_fmaf(-2.f, acc[qb][jj][r], nqj[jj][r]));
-        qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+      if (kb + 1 < NKB) {
+        acur[0] = anxt[0];
+        acur[1] = anxt[1];
       }
-      if (qbmask)
-        insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, bc0, bc1, band, kk,
-                           [&](int qb, int e) {
-                             return __builtin_fmaf(-2.f, acc[qb][e >> 2][e & 3], nqj[e >> 2][e & 3]);
-                           },
-                           t0h, bd.c1, wq0, lane, g, i16);
     }
+  };
+  // Screening filter of one half: lane holds rows t0h + jj*16 + 4g + r,
+  // query qb*16 + i16.
+  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h) {
+    unsigned qbmask = 0;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      float m = acc[qb][0][0];
+#pragma unroll
+      for (int e = 1; e < 8; ++e) m = fminf(m, acc[qb][e >> 2][e & 3]);
+      qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+    }
+    if (qbmask)
+      insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, bcw, band, kk,
+                         [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; },
+                         t0h, bd.c1, wq0, lane, g, i16);
+  };
+
+  // Software pipeline over halves: the products of the next half are issued
+  // before the filter (and any insertion) of the current one, so the matrix
+  // cores stay busy meanwhile.
+#pragma unroll
+  for (int it = 0; it < PIPE - 1; ++it) issue(it);
+  f32x4 accA[QB][2], accB[QB][2];
+  next_tile(0);
+  products(smem, 0, accA);
+  int tc = tstart;   // tile being computed
+  for (int it = 0; it < ntile; ++it) {
+    const char* tile = smem + (it & (PIPE - 1)) * STG;
+    const int t0 = bd.c0 + tc * BN;
+    tc = tc + 1 == ntile ? 0 : tc + 1;
+    products(tile, 1, accB);
+    filter(accA, t0);
+    if (it + 1 < ntile) {
+      next_tile(it + 1);
+      products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
+    }
+    filter(accB, t0 + 32);
   }
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 
@@ -1245,7 +1281,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
     if (p.KC == 32 && p.nkb <= 4) {
       p.piped = true;
-      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256);
+      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256) + 256 * sizeof(float2);
     }
   } else {
     const int cdim = KCH / p.esz;               // dims per K chunk
