@@ -566,8 +566,11 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   // Loads of a tile into a stage: chunk slot p of the stage holds chunk
   // (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
   // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
-  // its slot.  Every thread issues NKB + 1 loads per tile (rows past the
-  // cloud re-read valid data), which keeps the vmcnt bookkeeping static.
+  // its slot; its byte offset from the tile's first row is the same for
+  // every tile.  The screening copy and its norms hold 64 padding rows past
+  // the last cloud, so a tile never reads outside them (rows past a cloud
+  // never enter a list).  Every thread issues NKB + 1 loads per tile, which
+  // keeps the vmcnt bookkeeping static.
   // Scan order: tiles tstart, tstart + 1, ... cyclically.  With a spatial
   // order (perm != null: rows of Xq are the points perm[.], grouped by
   // nearest pivot) tstart is the tile of the block's own first query, so the
@@ -576,21 +579,23 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
   const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
   int tl = tstart;   // next tile to load
+  unsigned voff[NKB];
+#pragma unroll
+  for (int i = 0; i < NKB; ++i) {
+    const int p = tid + 256 * i;
+    const int r = p / cpr, sc = p - r * cpr;
+    voff[i] = (unsigned)(r * RS + ((sc ^ (r & smask)) << 4));
+  }
   auto issue = [&](int stg) {
     const int t0 = bd.c0 + tl * BN;
     tl = tl + 1 == ntile ? 0 : tl + 1;
     char* stage = smem + stg * STG;
+    const char* tb = Xb + (int64_t)t0 * RS;
 #pragma unroll
-    for (int i = 0; i < NKB; ++i) {
-      const int p = tid + 256 * i;
-      const int r = p / cpr, sc = p - r * cpr;
-      const int row = min(t0 + r, bd.c1 - 1);
-      const char* src = Xb + (int64_t)row * RS + ((sc ^ (r & smask)) << 4);
-      char* dst = stage + (256 * i + 64 * wave) * 16;
-      __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 0, 0);
-    }
-    const int row = min(t0 + lane, bd.c1 - 1);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + row), (lptr_t)(stage + TILE), 4, 0, 0);
+    for (int i = 0; i < NKB; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(tb + voff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
+                                       16, 0, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + lane), (lptr_t)(stage + TILE), 4, 0, 0);
   };
   // one tile consumed by every thread: wait for the next tile's loads, let
   // every wave pass, and refill the stage the consumed tile used
@@ -1455,8 +1460,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   const int esz = p.esz;
 
   Carve cv(ws);
-  void* Xq = cv.take<char>((size_t)n * p.DP * esz);
-  float* nq = cv.take<float>(n);
+  // the screening copy and its norms end with 64 zero rows (tile reads of
+  // the pipelined kernel run up to 63 rows past a cloud)
+  void* Xq = cv.take<char>((size_t)(n + 64) * p.DP * esz);
+  float* nq = cv.take<float>(n + 64);
   float* scl = cv.take<float>(n);
   float* qerr = cv.take<float>(n);
   unsigned* gstat = cv.take<unsigned>(4);
@@ -1472,8 +1479,8 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   // spatial order of the scan (one large cloud, pipelined screening)
   const bool spatial = p.piped && B == 1 && n >= 32768;
   const size_t sn = spatial ? (size_t)n : 0;
-  char* Xp = cv.take<char>(sn * p.DP * esz);
-  float* nqp = cv.take<float>(sn);
+  char* Xp = cv.take<char>((sn ? sn + 64 : 0) * p.DP * esz);
+  float* nqp = cv.take<float>(sn ? sn + 64 : 0);
   float* qerrp = cv.take<float>(sn);
   uint32_t* pkey = cv.take<uint32_t>(sn);
   uint32_t* pkey2 = cv.take<uint32_t>(sn);
@@ -1500,9 +1507,13 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e3 = hipMemsetAsync(gstat, 0, 16, s);
   hipError_t e4 = hipMemsetAsync(ctr, 0, 32, s);
   hipError_t e6 = hipMemsetAsync(ovf, 0, sizeof(int), s);
+  hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)64 * p.DP * esz, s);
+  hipError_t e8 = hipMemsetAsync(nq + n, 0, 64 * sizeof(float), s);
+  hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)64 * p.DP * esz, s) : hipSuccess;
+  hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 64 * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
-  if (e1 || e2 || e3 || e4 || e5 || e6) return FAMST_EHIP;
+  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10) return FAMST_EHIP;
 
   const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
   if (prec == FAMST_FP32)
