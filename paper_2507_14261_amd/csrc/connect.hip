@@ -71,13 +71,16 @@ __device__ __forceinline__ int uf_find(int* parent, int x) {
 }
 
 // Thread t takes edge (t * stride) mod (n k), a bijection for a stride
-// coprime to n k: concurrent threads then work on unrelated vertices, not
-// on neighbouring entries of parent[] (atomics on one cache line serialise).
+// coprime to n k.  With many small clouds the host passes a large stride:
+// concurrent threads then work on unrelated clouds rather than on one
+// cloud whose edges soon share a root (atomics on one address serialise).
+// One cloud is taken in order (stride 1: coalesced reads).
 __global__ void uf_hook_kernel(const int32_t* __restrict__ nbr, int64_t n, int k, uint64_t stride,
                                int* __restrict__ parent) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * k) return;
-  const int64_t e = (int64_t)(((unsigned __int128)t * stride) % (unsigned __int128)(n * k));
+  const int64_t e =
+      stride == 1 ? t : (int64_t)(((unsigned __int128)t * stride) % (unsigned __int128)(n * k));
   int a = (int)(e / k), b = nbr[e];
   if (b < 0 || b >= n) return;
   while (true) {
@@ -274,8 +277,11 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, rowcnt, row_ptr, n + 1, s));
   // ---- components
   FAMST_TRY(iota_i32(parent, n, s));
-  uint64_t stride = 1000003;   // odd, coprime to n k (checked)
-  while (std::gcd(stride, (uint64_t)(n * k)) != 1) stride += 2;
+  uint64_t stride = 1;   // one cloud: in order; several: odd, coprime to n k (checked)
+  if (B > 1) {
+    stride = 1000003;
+    while (std::gcd(stride, (uint64_t)(n * k)) != 1) stride += 2;
+  }
   FAMST_TRY(launch("uf_hook", uf_hook_kernel, dim3(cdiv(n * k, 256)), dim3(256), 0, s, nbr, n, k,
                    stride % (uint64_t)(n * k), parent));
   FAMST_TRY(launch("uf_roots", uf_roots_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, parent, n,
