@@ -75,19 +75,22 @@ __global__ void edge_compact_kernel(const uint64_t* __restrict__ keys, const uin
 // Live edges only (ids in `live`): drop edges inside one component, and
 // lower the per-component minimum key; a plain read first skips the atomic
 // for the (common) edges that cannot improve it.
-// Thread t takes live entry (t * stride) mod nlive (a bijection: the stride is
-// coprime to nlive).  With many small clouds the host passes a large stride,
-// so that concurrent atomics hit unrelated components rather than the few
-// components of one cloud; one cloud is taken in order (stride 1: coalesced
-// reads).
+// The live entries are taken in chunks of 64 (one wave, coalesced reads):
+// wave w takes chunk (w * stride) mod nchunk, a bijection for a stride
+// coprime to nchunk.  With many small clouds the host passes a large stride,
+// so that concurrent waves lower the minima of unrelated clouds rather than
+// the few components of one cloud; one cloud is taken in order (stride 1).
 __global__ void bv_min_edge_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
                                    const uint32_t* __restrict__ ewb, const uint32_t* __restrict__ live,
                                    int64_t nlive, uint64_t stride, const int32_t* __restrict__ comp,
                                    unsigned long long* __restrict__ best, int64_t* __restrict__ keep) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nlive) return;
-  const int64_t i =
-      stride == 1 ? t : (int64_t)(((unsigned __int128)t * stride) % (unsigned __int128)nlive);
+  const int64_t nchunk = (nlive + 63) >> 6, w = t >> 6;
+  if (w >= nchunk) return;
+  const int64_t c =
+      stride == 1 ? w : (int64_t)(((unsigned __int128)w * stride) % (unsigned __int128)nchunk);
+  const int64_t i = (c << 6) + (t & 63);
+  if (i >= nlive) return;
   const uint32_t e = live[i];
   int cu = comp[elo[e]], cv = comp[ehi[e]];
   if (cu == cv) {
@@ -727,13 +730,16 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
     for (int round = 0; round < 64 && nlive > 0; ++round) {
       FAMST_TRY(fill_u64(reinterpret_cast<uint64_t*>(best), KEY_NONE, n, s));
       FAMST_HIP(hipMemsetAsync(hooked, 0, sizeof(int), s));
-      uint64_t stride = 1;   // one cloud: in order; several: odd, coprime to nlive (checked)
+      // chunks of 64 live entries; one cloud: in order; several: a stride
+      // coprime to the chunk count (checked)
+      const uint64_t nchunk = (uint64_t)(nlive + 63) / 64;
+      uint64_t stride = 1;
       if (B > 1) {
-        stride = 1000003;
-        while (std::gcd(stride, (uint64_t)nlive) != 1) stride += 2;
+        stride = 1009;
+        while (std::gcd(stride, nchunk) != 1) stride += 2;
       }
       FAMST_TRY(launch("boruvka_min", bv_min_edge_kernel, dim3(cdiv(nlive, 256)), dim3(256), 0, s, elo,
-                       ehi, ewb, cur, nlive, stride % (uint64_t)nlive, comp, best, flag));
+                       ehi, ewb, cur, nlive, stride % nchunk, comp, best, flag));
       FAMST_TRY(launch("boruvka_hook", bv_hook_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, elo, ehi,
                        n, comp, best, P, in_tree, hooked));
       FAMST_TRY(launch("boruvka_jump", bv_jump_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, comp, n,
