@@ -32,14 +32,14 @@ HBM_GBS = 8000.0
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "26d4663e36932b0935a1887f0795a7444ad01ae0",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "259c22b6ebf0d576483a18d2714b4130ca98298b",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 958.9, "write_GB": 0.288,
+        "fetch_GB": 974.3, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "e462bedc387072cafa6da5aa3b90c663927b3d87",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "3a63161b4bbd18bba18885c52e54fc712cf31f6e",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 788.6, "write_GB": 0.41,
+        "fetch_GB": 799.6, "write_GB": 0.407,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
 }
 
