@@ -385,18 +385,6 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// 8-byte LDS read that waits for its own result inside the asm statement.
-// Ordinary LDS reads placed after direct global->LDS loads make the compiler
-// wait for every load in flight (it cannot tell which LDS bytes they
-// write); the band constants read here are never written by those loads.
-__device__ __forceinline__ float2 lds_read_f2(const float2* p) {
-  typedef float f2v __attribute__((ext_vector_type(2)));
-  f2v v;
-  const unsigned a = (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float2*)p;
-  asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(a) : "memory");
-  return float2{v.x, v.y};
-}
-
 // Screening band above the k-th screened value T of a query: wide enough
 // that the re-rank certificate (screening arithmetic error eps, input
 // rounding e = e_q + e_max, float32 near-tie factor tau) holds for every
@@ -433,7 +421,7 @@ struct Band {
 // the new k-th entry).
 template <int QB, int NE, class SpFn>
 __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbmask, float (&U)[QB],
-                                            const float (&nqq)[QB], const float2* bcw,
+                                            float nql, float bcl0, float bcl1,
                                             const Band& band, int kk,
                                             SpFn spf, int t0, int c1, int wq0, int lane, int g,
                                             int i16) {
@@ -461,7 +449,8 @@ __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbm
         const int qi = qb * 16 + (src & 15);
         const int L = qi >> 1, h = qi & 1;
         const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
-        const float nqv = readlane_f(nqq[qb], src);
+        const int qw = qb * 16 + (src & 15);   // query within the wave
+        const float nqv = readlane_f(nql, qw);
         const float s = spv + nqv;
         const float cs = ls[L];
         const int cjv = lj[L];
@@ -479,8 +468,7 @@ __device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbm
         ls[L] = ns;
         lj[L] = nj;
         const float Tk = readlane_f(ns, 32 * h + kk - 1);
-        const float2 bcv = lds_read_f2(bcw + qb * 16 + (src & 15));
-        const float Un = (Tk - nqv) + band(Tk, bcv.x, bcv.y);
+        const float Un = (Tk - nqv) + band(Tk, readlane_f(bcl0, qw), readlane_f(bcl1, qw));
         U[qb] = (i16 == (src & 15)) ? Un : U[qb];
       }
     }
@@ -533,20 +521,22 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 
   // resident query fragments, scaled by -2 (exact): the products then
   // accumulate onto the row norms and yield the screened value
-  // |y|^2 - 2 x.y directly.  The band constants of the wave's 64 queries
-  // sit in LDS after the stages (only insertions read them).
+  // |y|^2 - 2 x.y directly.  The norm and the band constants of the wave's
+  // query l sit in lane l (only insertions read them, by readlane).
   i32x4 qf[QB][NKB];
-  float nqq[QB], U[QB];
+  float U[QB];
   const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
-  float2* bcw = reinterpret_cast<float2*>(smem + PIPE * STG) + wave * QW;
+  float nql, bcl0, bcl1;
+  {
+    const int q = wq0 + lane;
+    const bool ok = q < bd.q1;
+    nql = ok ? nq[q] : 0.f;
+    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
+  }
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int q = wq0 + qb * 16 + i16;
     const bool ok = q < bd.q1;
-    nqq[qb] = ok ? nq[q] : 0.f;
-    float c0, c1;
-    band.consts(nqq[qb], ok ? qerr[q] : 0.f, c0, c1);
-    if (g == 0) bcw[qb * 16 + i16] = float2{c0, c1};
     U[qb] = ok ? F_INF : -F_INF;
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
@@ -665,7 +655,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
       qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
     }
     if (qbmask)
-      insert_regs<QB, 8>(ls, lj, qbmask, U, nqq, bcw, band, kk,
+      insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
                          [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; },
                          t0h, bd.c1, wq0, lane, g, i16);
   };
@@ -695,11 +685,14 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 
   // ---- write the candidate lists and the bound of the rejected elements
   // (rows and ids back in the caller's numbering under a spatial order)
+  float nqv[QB];   // norms of the lane's queries (every lane takes part in the shuffles)
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
   if (g == 0) {
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       const int q = wq0 + qb * 16 + i16;
-      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqq[qb];
+      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqv[qb];
     }
   }
   const int half = lane >> 5, rel = lane & 31;
@@ -1286,7 +1279,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
     if (p.KC == 32 && p.nkb <= 4) {
       p.piped = true;
-      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256) + 256 * sizeof(float2);
+      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256);
     }
   } else {
     const int cdim = KCH / p.esz;               // dims per K chunk
