@@ -708,6 +708,201 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   }
 }
 
+// ------------------------------------- high-dimensional screening, k' = 32
+// For rows longer than the register-resident queries allow (more than 128
+// bf16 or 64 float32 dimensions): a block of 256 queries (64 per wave, the
+// candidate lists in registers as in dist_topk_v2_kernel) against tiles of
+// 128 rows.  Queries and rows both stream through LDS in K-steps of 64 bytes
+// (32 bf16 or 16 float32 dimensions) by direct global->LDS loads into a ring
+// of HD_PIPE stages; each wave accumulates its 64 queries x 128 rows over
+// all K-steps of a tile, then filters and inserts as the pipelined kernel
+// does (same band, same bound of the rejected elements).  Every block scans
+// the tiles in the same ascending order, so the blocks resident at one time
+// read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
+// slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
+// LDS banks, so the operand reads are conflict-free.
+constexpr int HD_PIPE = 3, HD_BN = 128;
+constexpr int HD_SQ = 256 * 64;                  // query part of a stage (bytes)
+constexpr int HD_SR = HD_BN * 64;                // row part
+constexpr int HD_STG = HD_SQ + HD_SR + HD_BN * 4;  // + the tile's row norms
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
+    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
+    float tau, float* __restrict__ ubound) {
+  constexpr int QB = 4, KC = 32, QW = 64, JB = HD_BN / 16;
+  constexpr int NLD = 7;   // loads per thread per stage: 4 query chunks, 2 row chunks, 1 norm
+  const char* Xb = reinterpret_cast<const char*>(Xq_);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;
+  const int nks = RS >> 6;   // K-steps per row
+
+  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
+  float nql, bcl0, bcl1, U[QB];
+  {
+    const int q = wq0 + lane;
+    const bool ok = q < bd.q1;
+    nql = ok ? nq[q] : 0.f;
+    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
+  }
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) U[qb] = (wq0 + qb * 16 + i16 < bd.q1) ? F_INF : -F_INF;
+  f32x32 ls;
+  i32x32 lj;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    ls[L] = F_INF;
+    lj[L] = 0x7FFFFFFF;
+  }
+
+  // this thread's source offsets within the staged query block and row tile
+  // (the copy holds 256 padding rows past its end: no clamps)
+  unsigned qoff[4], roff[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int p = tid + 256 * i, r = p >> 2;
+    qoff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int p = tid + 256 * i, r = p >> 2;
+    roff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+  }
+  const int ntile = (bd.c1 - bd.c0 + HD_BN - 1) / HD_BN;
+  const char* qbase = Xb + (int64_t)bd.q0 * RS;
+  int lt = 0, lk = 0;   // tile and K-step of the next stage to load
+  auto issue = [&](int stg) {
+    const int t0 = bd.c0 + lt * HD_BN;
+    const int kofs = lk * 64;
+    if (++lk == nks) {
+      lk = 0;
+      lt = lt + 1 == ntile ? 0 : lt + 1;
+    }
+    char* stage = smem + stg * HD_STG;
+    const char* qb_ = qbase + kofs;
+    const char* rb_ = Xb + (int64_t)t0 * RS + kofs;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(qb_ + qoff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
+                                       16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(rb_ + roff[i]),
+                                       (lptr_t)(stage + HD_SQ + (256 * i + 64 * wave) * 16), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + (wave & 1) * 64 + lane),
+                                     (lptr_t)(stage + HD_SQ + HD_SR + (wave & 1) * 256), 4, 0, 0);
+  };
+
+  f32x4 acc[QB][JB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
+  const int nst = ntile * nks;
+  int cs = 0, ct = 0, ck = 0;   // stage slot, tile and K-step being computed
+  for (int st = 0; st < nst; ++st) {
+    wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
+    __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
+    issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
+    const char* stage = smem + cs * HD_STG;
+    // query fragments of this wave (B) and row fragments (A), one K-step
+    i32x4 bq[QB];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int r = wave * QW + qb * 16 + i16;
+      bq[qb] = *reinterpret_cast<const i32x4*>(stage + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+    }
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      const int r = jb * 16 + i16;
+      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + HD_SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        if constexpr (PREC == FAMST_FP32) {
+          const f32x4 af = __builtin_bit_cast(f32x4, a);
+          const f32x4 bf = __builtin_bit_cast(f32x4, bq[qb]);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
+        } else {
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bq[qb]), acc[qb][jb], 0, 0, 0);
+        }
+      }
+    }
+    if (++ck == nks) {
+      // tile complete: screened value |y|^2 - 2 x.y, filter and insertion in
+      // four groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
+      const int t0 = bd.c0 + ct * HD_BN;
+      const float* tn = reinterpret_cast<const float*>(stage + HD_SQ + HD_SR);
+#pragma unroll
+      for (int h = 0; h < JB / 2; ++h) {
+        float nqj[2][4];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * h + jj) * 16 + 4 * g);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
+        }
+        unsigned qbmask = 0;
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          float m = F_INF;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            m = fminf(m, __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]));
+          qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+        }
+        if (qbmask)
+          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
+                             [&](int qb, int e) {
+                               return __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
+                             },
+                             t0 + 32 * h, bd.c1, wq0, lane, g, i16);
+      }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ck = 0;
+      ++ct;
+    }
+    cs = cs + 1 == HD_PIPE ? 0 : cs + 1;
+  }
+  wait_vmcnt<0>();   // no load may land in LDS after the block ends
+
+  float nqv[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
+  if (g == 0) {
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int q = wq0 + qb * 16 + i16;
+      if (q < bd.q1) ubound[q] = U[qb] + nqv[qb];
+    }
+  }
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    const int q = wq0 + 2 * L + half;
+    if (q < bd.q1) {
+      cand_s[(int64_t)q * KC + rel] = ls[L];
+      cand_j[(int64_t)q * KC + rel] = lj[L];
+    }
+  }
+}
+
 // --------------------------------------------- spatial order of the scan
 // Every point (row of the screening copy) is assigned to the nearest of
 // NPIV pivot rows (rows floor(i n / NPIV)) by screened squared distance
@@ -1259,6 +1454,7 @@ struct KnnPlan {
   int prec, KC, DP, nkb, QB, qblk, esz;
   bool chunked;   // K-chunked kernel (any d, float8) instead of resident queries
   bool piped;     // register lists + pipelined tiles (k' = 32, up to 128 bf16 / 64 fp32 dims)
+  bool hd;        // register lists, queries and rows streamed by K-steps (k' = 32, beyond 128 dims)
   size_t lds;
 };
 
@@ -1272,7 +1468,16 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.nkb = (d + kbw - 1) / kbw;
   p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
   p.piped = false;
-  if (!p.chunked) {
+  p.hd = false;
+  if (prec != FAMST_FP8_E4M3 && p.KC == 32 && d > 128) {
+    const int kdim = 64 / p.esz;   // dimensions per 64-byte K-step
+    p.chunked = false;
+    p.hd = true;
+    p.DP = (d + kdim - 1) / kdim * kdim;
+    p.QB = 4;
+    p.qblk = 256;
+    p.lds = (size_t)HD_PIPE * HD_STG;
+  } else if (!p.chunked) {
     p.DP = p.nkb * kbw;
     p.QB = (p.KC == 64) ? 2 : 4;
     p.qblk = 64 * p.QB;
@@ -1353,6 +1558,20 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
                 ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);
+}
+
+template <int PREC>
+static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
+                     const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
+  auto kern = dist_topk_hd_kernel<PREC>;
+  static bool attr = false;
+  if (!attr) {
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr = true;
+  }
+  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.DP * p.esz, desc, cj, cs,
+                ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
 }
 
 template <int PREC>
@@ -1453,10 +1672,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   const int esz = p.esz;
 
   Carve cv(ws);
-  // the screening copy and its norms end with 64 zero rows (tile reads of
-  // the pipelined kernel run up to 63 rows past a cloud)
-  void* Xq = cv.take<char>((size_t)(n + 64) * p.DP * esz);
-  float* nq = cv.take<float>(n + 64);
+  // the screening copy and its norms end with 256 zero rows (tile and query
+  // block reads of the pipelined kernels run up to 255 rows past a cloud)
+  void* Xq = cv.take<char>((size_t)(n + 256) * p.DP * esz);
+  float* nq = cv.take<float>(n + 256);
   float* scl = cv.take<float>(n);
   float* qerr = cv.take<float>(n);
   unsigned* gstat = cv.take<unsigned>(4);
@@ -1472,8 +1691,8 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   // spatial order of the scan (one large cloud, pipelined screening)
   const bool spatial = p.piped && B == 1 && n >= 32768;
   const size_t sn = spatial ? (size_t)n : 0;
-  char* Xp = cv.take<char>((sn ? sn + 64 : 0) * p.DP * esz);
-  float* nqp = cv.take<float>(sn ? sn + 64 : 0);
+  char* Xp = cv.take<char>((sn ? sn + 256 : 0) * p.DP * esz);
+  float* nqp = cv.take<float>(sn ? sn + 256 : 0);
   float* qerrp = cv.take<float>(sn);
   uint32_t* pkey = cv.take<uint32_t>(sn);
   uint32_t* pkey2 = cv.take<uint32_t>(sn);
@@ -1500,10 +1719,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e3 = hipMemsetAsync(gstat, 0, 16, s);
   hipError_t e4 = hipMemsetAsync(ctr, 0, 32, s);
   hipError_t e6 = hipMemsetAsync(ovf, 0, sizeof(int), s);
-  hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)64 * p.DP * esz, s);
-  hipError_t e8 = hipMemsetAsync(nq + n, 0, 64 * sizeof(float), s);
-  hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)64 * p.DP * esz, s) : hipSuccess;
-  hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 64 * sizeof(float), s) : hipSuccess;
+  hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)256 * p.DP * esz, s);
+  hipError_t e8 = hipMemsetAsync(nq + n, 0, 256 * sizeof(float), s);
+  hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)256 * p.DP * esz, s) : hipSuccess;
+  hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
   if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10) return FAMST_EHIP;
@@ -1538,6 +1757,9 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   }
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
+  else if (p.hd)
+    FAMST_TRY(prec == FAMST_FP32 ? launch_hd<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs, ba)
+                                 : launch_hd<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
   else if (prec == FAMST_FP32)
     FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
   else
@@ -1547,7 +1769,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   ra.X = X; ra.n = n; ra.d = d; ra.offs = offs_d; ra.B = B; ra.k = k; ra.KC = p.KC;
   ra.cand_j = cj; ra.cand_s = cs; ra.nq = nq; ra.qerr = qerr; ra.gstat = gstat;
   ra.arith_c = arith_c;
-  ra.ubound = p.piped ? ub : nullptr;
+  ra.ubound = (p.piped || p.hd) ? ub : nullptr;
   ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_rows = bad; ra.counters = ctr;
   FAMST_TRY(launch("rerank", rerank_kernel, dim3((unsigned)n), dim3(64), 0, s, ra));
 

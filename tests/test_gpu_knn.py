@@ -128,3 +128,39 @@ def test_knn_lowrank_d960_precisions():
     assert rec["fp8"] >= 0.9
     nbr, dist, st = _run(X, 20, precision="fp8", exact=True)
     _check_exact(X, 20, nbr, dist)
+
+
+# Beyond 128 dimensions (bf16 or float32, k' = 32) queries and rows both
+# stream through LDS by K-steps: ragged query blocks and tiles, dimensions
+# just past the threshold and padded to a K-step, batched clouds.
+@pytest.mark.parametrize("n,d,k,prec", [(1100, 150, 12, "bf16"), (257, 129, 20, "fp32"),
+                                        (2000, 512, 16, "bf16"), (700, 960, 8, "fp32"),
+                                        (513, 200, 24, "bf16")])
+def test_knn_high_dim_matches_oracle(n, d, k, prec):
+    print(f"case n={n} d={d} k={k} {prec}", flush=True)
+    X = datagen.blobs(n=n, d=d, n_clusters=6, seed=n + d)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True)
+    print("stats", st, flush=True)
+    _check_exact(X, k, nbr, dist)
+
+
+def test_knn_high_dim_batched_clouds():
+    X, offs = datagen.clouds(n_clouds=4, lo=60, hi=600, d=200, seed=5)
+    nbr, dist, st = _run(X, 9, precision="bf16", exact=True, offs=offs)
+    for b in range(4):
+        sl = slice(offs[b], offs[b + 1])
+        ref_n, ref_s = oracle.knn_exact(X[sl], 9)
+        got = nbr[sl] - offs[b]
+        assert np.all(got >= 0) and np.all(got < offs[b + 1] - offs[b])
+        for i in range(len(ref_n)):
+            assert set(got[i].tolist()) == set(ref_n[i].tolist())
+
+
+def test_knn_high_dim_integer_data_bf16_equals_fp32_bitwise():
+    X = datagen.gamma_int(n=1500, d=256, n_clusters=10, seed=2)
+    a = _run(X, 20, precision="fp32", exact=True)
+    b = _run(X, 20, precision="bf16", exact=False)
+    assert b[2]["uncertified"] == 0, b[2]
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+    _check_exact(X, 20, a[0], a[1])
