@@ -1469,7 +1469,9 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
   p.piped = false;
   p.hd = false;
-  if (prec != FAMST_FP8_E4M3 && p.KC == 32 && d > 128) {
+  // beyond the register-resident queries (and for float32 beyond 64 dims,
+  // where the streamed operands cost less than the LDS-list kernel's waits)
+  if (prec != FAMST_FP8_E4M3 && p.KC == 32 && (d > 128 || (prec == FAMST_FP32 && d > 64))) {
     const int kdim = 64 / p.esz;   // dimensions per 64-byte K-step
     p.chunked = false;
     p.hd = true;
