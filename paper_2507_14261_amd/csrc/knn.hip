@@ -373,6 +373,12 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
 // (ls, lj), lanes 32 (qi & 1) .. 32 (qi & 1) + 31, ascending by (s, j).
 typedef float f32x32 __attribute__((ext_vector_type(32)));
 typedef int i32x32 __attribute__((ext_vector_type(32)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+typedef int i32x16v __attribute__((ext_vector_type(16)));
+// register lists of a wave with QW queries: QW / 2 register pairs
+template <int QW> struct ListRegs;
+template <> struct ListRegs<64> { using S = f32x32; using J = i32x32; };
+template <> struct ListRegs<32> { using S = f32x16v; using J = i32x16v; };
 typedef __attribute__((address_space(1))) const void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
 constexpr int PIPE = 4;
@@ -419,8 +425,8 @@ struct Band {
 // and each is inserted in turn into its query's list (a ballot gives the
 // position, DPP wave_shr:1 shifts the tail, the query's threshold follows
 // the new k-th entry).
-template <int QB, int NE, class SpFn>
-__device__ __forceinline__ void insert_regs(f32x32& ls, i32x32& lj, unsigned qbmask, float (&U)[QB],
+template <int QB, int NE, class LS, class LJ, class SpFn>
+__device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB],
                                             float nql, float bcl0, float bcl1,
                                             const Band& band, int kk,
                                             SpFn spf, int t0, int c1, int wq0, int lane, int g,
@@ -721,19 +727,32 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 // read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
 // slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
 // LDS banks, so the operand reads are conflict-free.
-constexpr int HD_PIPE = 3, HD_BN = 128;
-constexpr int HD_SQ = 256 * 64;                  // query part of a stage (bytes)
-constexpr int HD_SR = HD_BN * 64;                // row part
-constexpr int HD_STG = HD_SQ + HD_SR + HD_BN * 4;  // + the tile's row norms
+constexpr int HD_PIPE = 3;
+// Block shapes: NW waves of 16 QB queries (256 queries per block) against
+// tiles of BN rows; each wave accumulates QB x BN / 16 fragments (128 VGPRs).
+// bf16 takes the square 256 x 256 block (the streamed bytes per product
+// are smallest: 36 % against 24 % of the matrix-core peak at 960 dims);
+// float32, four times slower per byte on the matrix cores, takes
+// 256 x 128 with two blocks per CU.
+template <int NW> struct HdShape;
+template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128; };
+template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256; };
+template <int NW>
+constexpr size_t hd_stage_bytes() { return (size_t)256 * 64 + (size_t)HdShape<NW>::BN * 68; }
 
-template <int PREC>
-__global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
+template <int PREC, int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
     float tau, float* __restrict__ ubound) {
-  constexpr int QB = 4, KC = 32, QW = 64, JB = HD_BN / 16;
-  constexpr int NLD = 7;   // loads per thread per stage: 4 query chunks, 2 row chunks, 1 norm
+  constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
+  constexpr int NT = 64 * NW;
+  constexpr int SQ = 256 * 64, SR = BN * 64, STG = (int)hd_stage_bytes<NW>();
+  constexpr int NLQ = 1024 / NT, NLR = BN * 4 / NT;   // 16-byte query / row chunks per thread
+  constexpr int NLD = NLQ + NLR + 1;                  // loads per thread per stage (+ one norm)
+  using LS = typename ListRegs<QW>::S;
+  using LJ = typename ListRegs<QW>::J;
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
 
@@ -748,56 +767,58 @@ __global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
   float nql, bcl0, bcl1, U[QB];
   {
     const int q = wq0 + lane;
-    const bool ok = q < bd.q1;
+    const bool ok = lane < QW && q < bd.q1;
     nql = ok ? nq[q] : 0.f;
     band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
   }
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) U[qb] = (wq0 + qb * 16 + i16 < bd.q1) ? F_INF : -F_INF;
-  f32x32 ls;
-  i32x32 lj;
+  LS ls;
+  LJ lj;
 #pragma unroll
-  for (int L = 0; L < 32; ++L) {
+  for (int L = 0; L < QW / 2; ++L) {
     ls[L] = F_INF;
     lj[L] = 0x7FFFFFFF;
   }
 
   // this thread's source offsets within the staged query block and row tile
   // (the copy holds 256 padding rows past its end: no clamps)
-  unsigned qoff[4], roff[2];
+  unsigned qoff[NLQ], roff[NLR];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int p = tid + 256 * i, r = p >> 2;
+  for (int i = 0; i < NLQ; ++i) {
+    const int p = tid + NT * i, r = p >> 2;
     qoff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int p = tid + 256 * i, r = p >> 2;
+  for (int i = 0; i < NLR; ++i) {
+    const int p = tid + NT * i, r = p >> 2;
     roff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
   }
-  const int ntile = (bd.c1 - bd.c0 + HD_BN - 1) / HD_BN;
+  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
   const char* qbase = Xb + (int64_t)bd.q0 * RS;
   int lt = 0, lk = 0;   // tile and K-step of the next stage to load
   auto issue = [&](int stg) {
-    const int t0 = bd.c0 + lt * HD_BN;
+    const int t0 = bd.c0 + lt * BN;
     const int kofs = lk * 64;
     if (++lk == nks) {
       lk = 0;
       lt = lt + 1 == ntile ? 0 : lt + 1;
     }
-    char* stage = smem + stg * HD_STG;
+    char* stage = smem + stg * STG;
     const char* qb_ = qbase + kofs;
     const char* rb_ = Xb + (int64_t)t0 * RS + kofs;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      __builtin_amdgcn_global_load_lds((gptr_t)(qb_ + qoff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
+    for (int i = 0; i < NLQ; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(qb_ + qoff[i]), (lptr_t)(stage + (NT * i + 64 * wave) * 16),
                                        16, 0, 0);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NLR; ++i)
       __builtin_amdgcn_global_load_lds((gptr_t)(rb_ + roff[i]),
-                                       (lptr_t)(stage + HD_SQ + (256 * i + 64 * wave) * 16), 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + (wave & 1) * 64 + lane),
-                                     (lptr_t)(stage + HD_SQ + HD_SR + (wave & 1) * 256), 4, 0, 0);
+                                       (lptr_t)(stage + SQ + (NT * i + 64 * wave) * 16), 16, 0, 0);
+    // the BN norms: wave w fetches norms 64 (w mod BN/64) .. + 63 (duplicates write equal values)
+    const int nw = wave & (BN / 64 - 1);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + nw * 64 + lane),
+                                     (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
   };
 
   f32x4 acc[QB][JB];
@@ -814,7 +835,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
     wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
     issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
-    const char* stage = smem + cs * HD_STG;
+    const char* stage = smem + cs * STG;
     // query fragments of this wave (B) and row fragments (A), one K-step
     i32x4 bq[QB];
 #pragma unroll
@@ -825,7 +846,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
 #pragma unroll
     for (int jb = 0; jb < JB; ++jb) {
       const int r = jb * 16 + i16;
-      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + HD_SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
         if constexpr (PREC == FAMST_FP32) {
@@ -843,9 +864,9 @@ __global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
     }
     if (++ck == nks) {
       // tile complete: screened value |y|^2 - 2 x.y, filter and insertion in
-      // four groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
-      const int t0 = bd.c0 + ct * HD_BN;
-      const float* tn = reinterpret_cast<const float*>(stage + HD_SQ + HD_SR);
+      // groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
+      const int t0 = bd.c0 + ct * BN;
+      const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
 #pragma unroll
       for (int h = 0; h < JB / 2; ++h) {
         float nqj[2][4];
@@ -894,7 +915,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_hd_kernel(
   }
   const int half = lane >> 5, rel = lane & 31;
 #pragma unroll
-  for (int L = 0; L < 32; ++L) {
+  for (int L = 0; L < QW / 2; ++L) {
     const int q = wq0 + 2 * L + half;
     if (q < bd.q1) {
       cand_s[(int64_t)q * KC + rel] = ls[L];
@@ -1478,7 +1499,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.DP = (d + kdim - 1) / kdim * kdim;
     p.QB = 4;
     p.qblk = 256;
-    p.lds = (size_t)HD_PIPE * HD_STG;
+    p.lds = (size_t)HD_PIPE * (prec == FAMST_FP32 ? hd_stage_bytes<4>() : hd_stage_bytes<8>());
   } else if (!p.chunked) {
     p.DP = p.nkb * kbw;
     p.QB = (p.KC == 64) ? 2 : 4;
@@ -1562,18 +1583,18 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
                 ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);
 }
 
-template <int PREC>
+template <int PREC, int NW>
 static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                      const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
-  auto kern = dist_topk_hd_kernel<PREC>;
+  auto kern = dist_topk_hd_kernel<PREC, NW>;
   static bool attr = false;
   if (!attr) {
     FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
-  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.DP * p.esz, desc, cj, cs,
-                ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
+  return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), HD_PIPE * hd_stage_bytes<NW>(), s, Xq, nq,
+                p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
 }
 
 template <int PREC>
@@ -1760,8 +1781,8 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
   else if (p.hd)
-    FAMST_TRY(prec == FAMST_FP32 ? launch_hd<FAMST_FP32>(p, nblk, s, Xq, nq, desc, cj, cs, ba)
-                                 : launch_hd<FAMST_BF16>(p, nblk, s, Xq, nq, desc, cj, cs, ba));
+    FAMST_TRY((prec == FAMST_FP32 ? launch_hd<FAMST_FP32, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba)
+                                  : launch_hd<FAMST_BF16, 8>(p, nblk, s, Xq, nq, desc, cj, cs, ba)));
   else if (prec == FAMST_FP32)
     FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
   else
