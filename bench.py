@@ -32,10 +32,15 @@ HBM_GBS = 8000.0
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "259c22b6ebf0d576483a18d2714b4130ca98298b",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "5f2446221a361c9c57ed6bce09d09cab8b84915c",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 974.3, "write_GB": 0.288,
+        "fetch_GB": 971.4, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
+    ("dist_topk", "lowrank-500k-d960"): {
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "5f2446221a361c9c57ed6bce09d09cab8b84915c",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
+        "fetch_GB": 1957.5, "write_GB": 0.130,
+        "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "3a63161b4bbd18bba18885c52e54fc712cf31f6e",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
