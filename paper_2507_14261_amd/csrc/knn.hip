@@ -716,29 +716,31 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
 
 // ------------------------------------- high-dimensional screening, k' = 32
 // For rows longer than the register-resident queries allow (more than 128
-// bf16 or 64 float32 dimensions): a block of 256 queries (64 per wave, the
-// candidate lists in registers as in dist_topk_v2_kernel) against tiles of
-// 128 rows.  Queries and rows both stream through LDS in K-steps of 64 bytes
-// (32 bf16 or 16 float32 dimensions) by direct global->LDS loads into a ring
-// of HD_PIPE stages; each wave accumulates its 64 queries x 128 rows over
-// all K-steps of a tile, then filters and inserts as the pipelined kernel
-// does (same band, same bound of the rejected elements).  Every block scans
+// bf16 or 64 float32 dimensions): a block of 256 queries (the candidate
+// lists in registers as in dist_topk_v2_kernel) against tiles of rows.
+// Queries and rows both stream through LDS in K-steps of 64 bytes (32 bf16
+// or 16 float32 dimensions) by direct global->LDS loads into a ring of
+// stages; each wave accumulates its queries x tile rows over all K-steps of
+// a tile, then filters and inserts as the pipelined kernel does (same band,
+// same bound of the rejected elements).  Every block scans
 // the tiles in the same ascending order, so the blocks resident at one time
 // read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
 // slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
 // LDS banks, so the operand reads are conflict-free.
-constexpr int HD_PIPE = 3;
 // Block shapes: NW waves of 16 QB queries (256 queries per block) against
-// tiles of BN rows; each wave accumulates QB x BN / 16 fragments (128 VGPRs).
-// bf16 takes the square 256 x 256 block (the streamed bytes per product
-// are smallest: 36 % against 24 % of the matrix-core peak at 960 dims);
-// float32, four times slower per byte on the matrix cores, takes
-// 256 x 128 with two blocks per CU.
+// tiles of BN rows in a ring of PIPE stages; each wave accumulates
+// QB x BN / 16 fragments (128 VGPRs).  bf16 takes the square 256 x 256
+// block (the streamed bytes per product are smallest: 36 % against 24 % of
+// the matrix-core peak at 960 dims) with one block per CU and four stages;
+// float32, four times slower per byte on the matrix cores, takes 256 x 128
+// with two blocks per CU and three stages.
 template <int NW> struct HdShape;
-template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128; };
-template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256; };
+template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3; };
+template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 4; };
 template <int NW>
 constexpr size_t hd_stage_bytes() { return (size_t)256 * 64 + (size_t)HdShape<NW>::BN * 68; }
+template <int NW>
+constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
 
 template <int PREC, int NW>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
@@ -747,6 +749,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
     float tau, float* __restrict__ ubound) {
   constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
+  constexpr int HD_PIPE = HdShape<NW>::PIPE;
   constexpr int NT = 64 * NW;
   constexpr int SQ = 256 * 64, SR = BN * 64, STG = (int)hd_stage_bytes<NW>();
   constexpr int NLQ = 1024 / NT, NLR = BN * 4 / NT;   // 16-byte query / row chunks per thread
@@ -1499,7 +1502,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.DP = (d + kdim - 1) / kdim * kdim;
     p.QB = 4;
     p.qblk = 256;
-    p.lds = (size_t)HD_PIPE * (prec == FAMST_FP32 ? hd_stage_bytes<4>() : hd_stage_bytes<8>());
+    p.lds = prec == FAMST_FP32 ? hd_lds_bytes<4>() : hd_lds_bytes<8>();
   } else if (!p.chunked) {
     p.DP = p.nkb * kbw;
     p.QB = (p.KC == 64) ? 2 : 4;
@@ -1593,7 +1596,7 @@ static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
-  return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), HD_PIPE * hd_stage_bytes<NW>(), s, Xq, nq,
+  return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), hd_lds_bytes<NW>(), s, Xq, nq,
                 p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
 }
 
