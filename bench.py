@@ -32,14 +32,16 @@ HBM_GBS = 8000.0
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "5f2446221a361c9c57ed6bce09d09cab8b84915c",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "1b15179f0b0498188ba34125ab07a24a815caa2e",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "b34b3ea57e914caa83962bcd9be83ac44b01e336",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 971.4, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "5f2446221a361c9c57ed6bce09d09cab8b84915c",
+        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "ee59911332734699ff3ed07670bed014a365d06d",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "b34b3ea57e914caa83962bcd9be83ac44b01e336",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 1957.5, "write_GB": 0.130,
+        "fetch_GB": 1997.9, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "3a63161b4bbd18bba18885c52e54fc712cf31f6e",

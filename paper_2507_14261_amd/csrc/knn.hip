@@ -5,6 +5,9 @@
 #include "famst_common.hpp"
 #include "prims.hpp"
 #include "select.hpp"
+#include "screen_regs.hpp"
+#include "screen_v2.hpp"
+#include "screen_hd.hpp"
 
 namespace famst {
 
@@ -78,33 +81,6 @@ __global__ __launch_bounds__(256) void prep_kernel(const float* __restrict__ X, 
     atomicMax(&gstat[2], m2);
   }
 }
-
-// ------------------------------------------------------ distance + top-k'
-// Work unit of one block: queries [q0, q1) of one cloud against the
-// cloud's rows [c0, c1).
-struct BlockDesc {
-  int q0, q1, c0, c1;
-};
-
-struct __attribute__((aligned(8))) Cand {
-  float s;
-  int j;
-};
-
-template <int PREC>
-struct Scr;
-template <>
-struct Scr<FAMST_FP32> {
-  using T = float;
-  static constexpr int KBW = 16;  // k covered by one 16-byte fragment per lane x 4 lane groups
-  static constexpr int ESZ = 4;
-};
-template <>
-struct Scr<FAMST_BF16> {
-  using T = uint16_t;
-  static constexpr int KBW = 32;
-  static constexpr int ESZ = 2;
-};
 
 // Squared-distance screening of 64*QB queries per wave (4 waves per block)
 // against 64-row tiles of the cloud, on the matrix cores:
@@ -358,571 +334,6 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
         cand_s[(int64_t)q * KC + lane] = c.s;
         cand_j[(int64_t)q * KC + lane] = c.j;
       }
-    }
-  }
-}
-
-// ------------------------------------------- pipelined screening, k' = 32
-// The products, filter and insertion rule of dist_topk_kernel, organised
-// for memory-level parallelism: the per-query lists live in registers,
-// which frees LDS for a ring of PIPE tile stages filled by direct
-// global->LDS loads, so PIPE-1 tiles are in flight while one is consumed and
-// a single barrier per tile suffices.
-//
-// Register lists: query qi (0..63) of a wave owns register pair qi/2 of
-// (ls, lj), lanes 32 (qi & 1) .. 32 (qi & 1) + 31, ascending by (s, j).
-typedef float f32x32 __attribute__((ext_vector_type(32)));
-typedef int i32x32 __attribute__((ext_vector_type(32)));
-typedef float f32x16v __attribute__((ext_vector_type(16)));
-typedef int i32x16v __attribute__((ext_vector_type(16)));
-// register lists of a wave with QW queries: QW / 2 register pairs
-template <int QW> struct ListRegs;
-template <> struct ListRegs<64> { using S = f32x32; using J = i32x32; };
-template <> struct ListRegs<32> { using S = f32x16v; using J = i32x16v; };
-typedef __attribute__((address_space(1))) const void* gptr_t;
-typedef __attribute__((address_space(3))) void* lptr_t;
-constexpr int PIPE = 4;
-static_assert((PIPE & (PIPE - 1)) == 0, "stage index by mask");
-
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  // gfx9 s_waitcnt: vmcnt in bits [3:0] and [15:14]; expcnt and lgkmcnt at
-  // their maxima (not waited for)
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Screening band above the k-th screened value T of a query: wide enough
-// that the re-rank certificate (screening arithmetic error eps, input
-// rounding e = e_q + e_max, float32 near-tie factor tau) holds for every
-// element the filter rejects:
-//   band(T) = (2 eps + 4 e^2) + 4 e sqrt(T) + (8 tau + 1e-5) |T|,
-// +inf while fewer than k entries exist.  Only the chance of certifying
-// depends on it: the certificate itself uses the final threshold, which
-// bounds every rejected element whatever the band was.
-struct Band {
-  float arith_c, nmax, emax, tau;
-  // per-query constants: c0 = 2 eps + 4 e^2, c1 = 4 e
-  __device__ __forceinline__ void consts(float nqv, float eqv, float& c0, float& c1) const {
-    const float e = eqv + emax;
-    c0 = 2.f * arith_c * (nqv + nmax) + 4.f * e * e;
-    c1 = 4.f * e;
-  }
-  __device__ __forceinline__ float operator()(float Tk, float c0, float c1) const {
-    if (!(Tk < F_INF)) return F_INF;
-    // hardware square root, rounded up by a few ulps
-    const float r = c1 > 0.f ? __builtin_amdgcn_sqrtf(fmaxf(Tk, 0.f)) * 1.000001f : 0.f;
-    return c0 + c1 * r + (8.f * tau + 1e-5f) * fabsf(Tk);
-  }
-};
-
-// The filter threshold of a query is U = T_k - |x_q|^2 + band(T_k) with T_k
-// the k-th entry of its list (not the last): an element screened above it
-// cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
-// rejected element for the certificate.
-//
-// Elements are taken element-major: for each of the NE elements a lane
-// holds (a static register), a ballot gives the lanes whose element passed,
-// and each is inserted in turn into its query's list (a ballot gives the
-// position, DPP wave_shr:1 shifts the tail, the query's threshold follows
-// the new k-th entry).
-template <int QB, int NE, class LS, class LJ, class SpFn>
-__device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB],
-                                            float nql, float bcl0, float bcl1,
-                                            const Band& band, int kk,
-                                            SpFn spf, int t0, int c1, int wq0, int lane, int g,
-                                            int i16) {
-  const int half = lane >> 5, rel = lane & 31;
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) {
-    if (!(qbmask & (1u << qb))) continue;
-    const int q = wq0 + qb * 16 + i16;
-    float sp[NE];
-    bool ok[NE];
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      sp[e] = spf(qb, e);
-      const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
-      ok[e] = (sp[e] <= U[qb]) & (j < c1) & (j != q);
-    }
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      unsigned long long lanes = ballot(ok[e]);
-      while (lanes) {
-        const int src = __builtin_ctzll(lanes);
-        lanes &= lanes - 1;
-        const float spv = readlane_f(sp[e], src);
-        if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
-        const int qi = qb * 16 + (src & 15);
-        const int L = qi >> 1, h = qi & 1;
-        const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
-        const int qw = qb * 16 + (src & 15);   // query within the wave
-        const float nqv = readlane_f(nql, qw);
-        const float s = spv + nqv;
-        const float cs = ls[L];
-        const int cjv = lj[L];
-        const bool mine = half == h;
-        const bool lt = mine & ((cs < s) | ((cs == s) & (cjv < j)));
-        const int pos = __builtin_popcountll(ballot(lt));
-        if (pos >= 32) continue;
-        // shift the tail of the half up by one (DPP wave_shr:1); the first
-        // lane of a half never takes the shifted value
-        const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cs), 0x138, 0xF, 0xF, false));
-        const int upj = __builtin_amdgcn_update_dpp(0, cjv, 0x138, 0xF, 0xF, false);
-        const bool keep = !mine | (rel < pos);
-        const float ns = keep ? cs : (rel == pos ? s : ups);
-        const int nj = keep ? cjv : (rel == pos ? j : upj);
-        ls[L] = ns;
-        lj[L] = nj;
-        const float Tk = readlane_f(ns, 32 * h + kk - 1);
-        const float Un = (Tk - nqv) + band(Tk, readlane_f(bcl0, qw), readlane_f(bcl1, qw));
-        U[qb] = (i16 == (src & 15)) ? Un : U[qb];
-      }
-    }
-  }
-}
-
-// A query fragment (8 bf16 or 4 float32 values) times -2; exact for every
-// finite input (a power-of-two scaling, far from overflow for rows that
-// passed the norm check).
-template <int PREC>
-__device__ __forceinline__ i32x4 neg2_fragment(i32x4 v) {
-  if constexpr (PREC == FAMST_FP32) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = __float_as_int(-2.f * __int_as_float(v[i]));
-    return v;
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const unsigned u = (unsigned)v[i];
-      const unsigned lo = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u & 0xFFFFu)));
-      const unsigned hi = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u >> 16)));
-      v[i] = (int)(lo | (hi << 16));
-    }
-    return v;
-  }
-}
-
-template <int PREC, int NKB>
-__global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
-    const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
-    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
-    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
-    float tau, float* __restrict__ ubound, const int* __restrict__ perm) {
-  using S = Scr<PREC>;
-  constexpr int QB = 4, KC = 32, QW = 64, BN = 64;
-  constexpr int TILE = BN * NKB * 64;   // 64 rows x NKB 64-byte chunks
-  constexpr int STG = TILE + 256;       // tile + its 64 norms
-  const char* Xb = reinterpret_cast<const char*>(Xq_);
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-
-  const BlockDesc bd = desc[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4, i16 = lane & 15;
-  const int wq0 = bd.q0 + wave * QW;
-  // instantiated for the exact number of K-blocks: no runtime guards in the
-  // tile loop (they would split it into branches and force full waits)
-  constexpr int RS = NKB * 64, cpr = NKB * 4;
-  constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
-
-  // resident query fragments, scaled by -2 (exact): the products then
-  // accumulate onto the row norms and yield the screened value
-  // |y|^2 - 2 x.y directly.  The norm and the band constants of the wave's
-  // query l sit in lane l (only insertions read them, by readlane).
-  i32x4 qf[QB][NKB];
-  float U[QB];
-  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
-  float nql, bcl0, bcl1;
-  {
-    const int q = wq0 + lane;
-    const bool ok = q < bd.q1;
-    nql = ok ? nq[q] : 0.f;
-    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
-  }
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) {
-    const int q = wq0 + qb * 16 + i16;
-    const bool ok = q < bd.q1;
-    U[qb] = ok ? F_INF : -F_INF;
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      i32x4 v = {0, 0, 0, 0};
-      if (ok) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
-      qf[qb][kb] = neg2_fragment<PREC>(v);
-    }
-  }
-  f32x32 ls;
-  i32x32 lj;
-#pragma unroll
-  for (int L = 0; L < 32; ++L) {
-    ls[L] = F_INF;
-    lj[L] = 0x7FFFFFFF;
-  }
-
-  // Loads of a tile into a stage: chunk slot p of the stage holds chunk
-  // (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
-  // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
-  // its slot; its byte offset from the tile's first row is the same for
-  // every tile.  The screening copy and its norms hold 64 padding rows past
-  // the last cloud, so a tile never reads outside them (rows past a cloud
-  // never enter a list).  Every thread issues NKB + 1 loads per tile, which
-  // keeps the vmcnt bookkeeping static.
-  // Scan order: tiles tstart, tstart + 1, ... cyclically.  With a spatial
-  // order (perm != null: rows of Xq are the points perm[.], grouped by
-  // nearest pivot) tstart is the tile of the block's own first query, so the
-  // likely neighbours come first and the thresholds tighten early.  Two
-  // scalar counters follow the tile to load and the tile to compute.
-  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
-  const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
-  int tl = tstart;   // next tile to load
-  unsigned voff[NKB];
-#pragma unroll
-  for (int i = 0; i < NKB; ++i) {
-    const int p = tid + 256 * i;
-    const int r = p / cpr, sc = p - r * cpr;
-    voff[i] = (unsigned)(r * RS + ((sc ^ (r & smask)) << 4));
-  }
-  auto issue = [&](int stg) {
-    const int t0 = bd.c0 + tl * BN;
-    tl = tl + 1 == ntile ? 0 : tl + 1;
-    char* stage = smem + stg * STG;
-    const char* tb = Xb + (int64_t)t0 * RS;
-#pragma unroll
-    for (int i = 0; i < NKB; ++i)
-      __builtin_amdgcn_global_load_lds((gptr_t)(tb + voff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
-                                       16, 0, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + lane), (lptr_t)(stage + TILE), 4, 0, 0);
-  };
-  // one tile consumed by every thread: wait for the next tile's loads, let
-  // every wave pass, and refill the stage the consumed tile used
-  auto next_tile = [&](int it) {
-    wait_vmcnt<(PIPE - 2) * (NKB + 1)>();   // this thread's loads of tile it are done
-    __builtin_amdgcn_s_barrier();           // ... and every thread's; tile it-1 is consumed
-    issue((it + PIPE - 1) & (PIPE - 1));    // into the stage tile it-1 used
-  };
-
-  // Products of one half (32 rows) of a tile: the accumulators start at the
-  // norms of their rows; A fragments double-buffered (the LDS reads of
-  // K-step kb + 1 are issued before the products of K-step kb).
-  auto products = [&](const char* tile, int jh, f32x4 (&acc)[QB][2]) {
-    const float* tn = reinterpret_cast<const float*>(tile + TILE);
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * jh + jj) * 16 + 4 * g);
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) acc[qb][jj] = v;
-    }
-    auto lda = [&](int kb, i32x4 (&a)[2]) {
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        const int r = (2 * jh + jj) * 16 + i16;
-        const int cc = kb * 4 + g;
-        a[jj] = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
-      }
-    };
-    i32x4 acur[2], anxt[2];
-    lda(0, acur);
-#pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      if (kb + 1 < NKB) lda(kb + 1, anxt);
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        const i32x4 a = acur[jj];
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-          if constexpr (PREC == FAMST_FP32) {
-            const f32x4 af = __builtin_bit_cast(f32x4, a);
-            const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
-            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jj], 0, 0, 0);
-            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jj], 0, 0, 0);
-            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jj], 0, 0, 0);
-            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jj], 0, 0, 0);
-          } else {
-            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
-          }
-        }
-      }
-      if (kb + 1 < NKB) {
-        acur[0] = anxt[0];
-        acur[1] = anxt[1];
-      }
-    }
-  };
-  // Screening filter of one half: lane holds rows t0h + jj*16 + 4g + r,
-  // query qb*16 + i16.
-  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h) {
-    unsigned qbmask = 0;
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      float m = acc[qb][0][0];
-#pragma unroll
-      for (int e = 1; e < 8; ++e) m = fminf(m, acc[qb][e >> 2][e & 3]);
-      qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
-    }
-    if (qbmask)
-      insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
-                         [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; },
-                         t0h, bd.c1, wq0, lane, g, i16);
-  };
-
-  // Software pipeline over halves: the products of the next half are issued
-  // before the filter (and any insertion) of the current one, so the matrix
-  // cores stay busy meanwhile.
-#pragma unroll
-  for (int it = 0; it < PIPE - 1; ++it) issue(it);
-  f32x4 accA[QB][2], accB[QB][2];
-  next_tile(0);
-  products(smem, 0, accA);
-  int tc = tstart;   // tile being computed
-  for (int it = 0; it < ntile; ++it) {
-    const char* tile = smem + (it & (PIPE - 1)) * STG;
-    const int t0 = bd.c0 + tc * BN;
-    tc = tc + 1 == ntile ? 0 : tc + 1;
-    products(tile, 1, accB);
-    filter(accA, t0);
-    if (it + 1 < ntile) {
-      next_tile(it + 1);
-      products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
-    }
-    filter(accB, t0 + 32);
-  }
-  wait_vmcnt<0>();   // no load may land in LDS after the block ends
-
-  // ---- write the candidate lists and the bound of the rejected elements
-  // (rows and ids back in the caller's numbering under a spatial order)
-  float nqv[QB];   // norms of the lane's queries (every lane takes part in the shuffles)
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
-  if (g == 0) {
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      const int q = wq0 + qb * 16 + i16;
-      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqv[qb];
-    }
-  }
-  const int half = lane >> 5, rel = lane & 31;
-#pragma unroll
-  for (int L = 0; L < 32; ++L) {
-    const int q = wq0 + 2 * L + half;
-    if (q < bd.q1) {
-      const int qo = perm ? perm[q] : q;
-      const int jv = lj[L];
-      cand_s[(int64_t)qo * KC + rel] = ls[L];
-      cand_j[(int64_t)qo * KC + rel] = (perm && jv != 0x7FFFFFFF) ? perm[jv] : jv;
-    }
-  }
-}
-
-// ------------------------------------- high-dimensional screening, k' = 32
-// For rows longer than the register-resident queries allow (more than 128
-// bf16 or 64 float32 dimensions): a block of 256 queries (the candidate
-// lists in registers as in dist_topk_v2_kernel) against tiles of rows.
-// Queries and rows both stream through LDS in K-steps of 64 bytes (32 bf16
-// or 16 float32 dimensions) by direct global->LDS loads into a ring of
-// stages; each wave accumulates its queries x tile rows over all K-steps of
-// a tile, then filters and inserts as the pipelined kernel does (same band,
-// same bound of the rejected elements).  Every block scans
-// the tiles in the same ascending order, so the blocks resident at one time
-// read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
-// slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
-// LDS banks, so the operand reads are conflict-free.
-// Block shapes: NW waves of 16 QB queries (256 queries per block) against
-// tiles of BN rows in a ring of PIPE stages; each wave accumulates
-// QB x BN / 16 fragments (128 VGPRs).  bf16 takes the square 256 x 256
-// block (the streamed bytes per product are smallest: 36 % against 24 % of
-// the matrix-core peak at 960 dims) with one block per CU and four stages;
-// float32, four times slower per byte on the matrix cores, takes 256 x 128
-// with two blocks per CU and three stages.
-template <int NW> struct HdShape;
-template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3; };
-template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 4; };
-template <int NW>
-constexpr size_t hd_stage_bytes() { return (size_t)256 * 64 + (size_t)HdShape<NW>::BN * 68; }
-template <int NW>
-constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
-
-template <int PREC, int NW>
-__global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
-    const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
-    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
-    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
-    float tau, float* __restrict__ ubound) {
-  constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
-  constexpr int HD_PIPE = HdShape<NW>::PIPE;
-  constexpr int NT = 64 * NW;
-  constexpr int SQ = 256 * 64, SR = BN * 64, STG = (int)hd_stage_bytes<NW>();
-  constexpr int NLQ = 1024 / NT, NLR = BN * 4 / NT;   // 16-byte query / row chunks per thread
-  constexpr int NLD = NLQ + NLR + 1;                  // loads per thread per stage (+ one norm)
-  using LS = typename ListRegs<QW>::S;
-  using LJ = typename ListRegs<QW>::J;
-  const char* Xb = reinterpret_cast<const char*>(Xq_);
-  extern __shared__ __attribute__((aligned(16))) char smem[];
-
-  const BlockDesc bd = desc[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4, i16 = lane & 15;
-  const int wq0 = bd.q0 + wave * QW;
-  const int nks = RS >> 6;   // K-steps per row
-
-  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
-  float nql, bcl0, bcl1, U[QB];
-  {
-    const int q = wq0 + lane;
-    const bool ok = lane < QW && q < bd.q1;
-    nql = ok ? nq[q] : 0.f;
-    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
-  }
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) U[qb] = (wq0 + qb * 16 + i16 < bd.q1) ? F_INF : -F_INF;
-  LS ls;
-  LJ lj;
-#pragma unroll
-  for (int L = 0; L < QW / 2; ++L) {
-    ls[L] = F_INF;
-    lj[L] = 0x7FFFFFFF;
-  }
-
-  // this thread's source offsets within the staged query block and row tile
-  // (the copy holds 256 padding rows past its end: no clamps)
-  unsigned qoff[NLQ], roff[NLR];
-#pragma unroll
-  for (int i = 0; i < NLQ; ++i) {
-    const int p = tid + NT * i, r = p >> 2;
-    qoff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
-  }
-#pragma unroll
-  for (int i = 0; i < NLR; ++i) {
-    const int p = tid + NT * i, r = p >> 2;
-    roff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
-  }
-  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
-  const char* qbase = Xb + (int64_t)bd.q0 * RS;
-  int lt = 0, lk = 0;   // tile and K-step of the next stage to load
-  auto issue = [&](int stg) {
-    const int t0 = bd.c0 + lt * BN;
-    const int kofs = lk * 64;
-    if (++lk == nks) {
-      lk = 0;
-      lt = lt + 1 == ntile ? 0 : lt + 1;
-    }
-    char* stage = smem + stg * STG;
-    const char* qb_ = qbase + kofs;
-    const char* rb_ = Xb + (int64_t)t0 * RS + kofs;
-#pragma unroll
-    for (int i = 0; i < NLQ; ++i)
-      __builtin_amdgcn_global_load_lds((gptr_t)(qb_ + qoff[i]), (lptr_t)(stage + (NT * i + 64 * wave) * 16),
-                                       16, 0, 0);
-#pragma unroll
-    for (int i = 0; i < NLR; ++i)
-      __builtin_amdgcn_global_load_lds((gptr_t)(rb_ + roff[i]),
-                                       (lptr_t)(stage + SQ + (NT * i + 64 * wave) * 16), 16, 0, 0);
-    // the BN norms: wave w fetches norms 64 (w mod BN/64) .. + 63 (duplicates write equal values)
-    const int nw = wave & (BN / 64 - 1);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + nw * 64 + lane),
-                                     (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
-  };
-
-  f32x4 acc[QB][JB];
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-#pragma unroll
-  for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
-  const int nst = ntile * nks;
-  int cs = 0, ct = 0, ck = 0;   // stage slot, tile and K-step being computed
-  for (int st = 0; st < nst; ++st) {
-    wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
-    __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
-    issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
-    const char* stage = smem + cs * STG;
-    // query fragments of this wave (B) and row fragments (A), one K-step
-    i32x4 bq[QB];
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      const int r = wave * QW + qb * 16 + i16;
-      bq[qb] = *reinterpret_cast<const i32x4*>(stage + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
-    }
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) {
-      const int r = jb * 16 + i16;
-      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        if constexpr (PREC == FAMST_FP32) {
-          const f32x4 af = __builtin_bit_cast(f32x4, a);
-          const f32x4 bf = __builtin_bit_cast(f32x4, bq[qb]);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
-        } else {
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bq[qb]), acc[qb][jb], 0, 0, 0);
-        }
-      }
-    }
-    if (++ck == nks) {
-      // tile complete: screened value |y|^2 - 2 x.y, filter and insertion in
-      // groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
-      const int t0 = bd.c0 + ct * BN;
-      const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
-#pragma unroll
-      for (int h = 0; h < JB / 2; ++h) {
-        float nqj[2][4];
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * h + jj) * 16 + 4 * g);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
-        }
-        unsigned qbmask = 0;
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-          float m = F_INF;
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            m = fminf(m, __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]));
-          qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
-        }
-        if (qbmask)
-          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
-                             [&](int qb, int e) {
-                               return __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
-                             },
-                             t0 + 32 * h, bd.c1, wq0, lane, g, i16);
-      }
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      ck = 0;
-      ++ct;
-    }
-    cs = cs + 1 == HD_PIPE ? 0 : cs + 1;
-  }
-  wait_vmcnt<0>();   // no load may land in LDS after the block ends
-
-  float nqv[QB];
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
-  if (g == 0) {
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      const int q = wq0 + qb * 16 + i16;
-      if (q < bd.q1) ubound[q] = U[qb] + nqv[qb];
-    }
-  }
-  const int half = lane >> 5, rel = lane & 31;
-#pragma unroll
-  for (int L = 0; L < QW / 2; ++L) {
-    const int q = wq0 + 2 * L + half;
-    if (q < bd.q1) {
-      cand_s[(int64_t)q * KC + rel] = ls[L];
-      cand_j[(int64_t)q * KC + rel] = lj[L];
     }
   }
 }

@@ -1,0 +1,220 @@
+// Screening with queries and rows streamed by K-steps (k' = 32, beyond 128 bf16 / 64 fp32 dims).
+#pragma once
+#include "screen_regs.hpp"
+
+namespace famst {
+
+// ------------------------------------- high-dimensional screening, k' = 32
+// For rows longer than the register-resident queries allow (more than 128
+// bf16 or 64 float32 dimensions): a block of 256 queries (the candidate
+// lists in registers as in dist_topk_v2_kernel) against tiles of rows.
+// Queries and rows both stream through LDS in K-steps of 64 bytes (32 bf16
+// or 16 float32 dimensions) by direct global->LDS loads into a ring of
+// stages; each wave accumulates its queries x tile rows over all K-steps of
+// a tile, then filters and inserts as the pipelined kernel does (same band,
+// same bound of the rejected elements).  Every block scans
+// the tiles in the same ascending order, so the blocks resident at one time
+// read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
+// slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
+// LDS banks, so the operand reads are conflict-free.
+// Block shapes: NW waves of 16 QB queries (256 queries per block) against
+// tiles of BN rows in a ring of PIPE stages; each wave accumulates
+// QB x BN / 16 fragments (128 VGPRs).  bf16 takes the square 256 x 256
+// block (the streamed bytes per product are smallest: 36 % against 24 % of
+// the matrix-core peak at 960 dims) with one block per CU and four stages;
+// float32, four times slower per byte on the matrix cores, takes 256 x 128
+// with two blocks per CU and three stages.
+template <int NW> struct HdShape;
+template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3; };
+template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 4; };
+template <int NW>
+constexpr size_t hd_stage_bytes() { return (size_t)256 * 64 + (size_t)HdShape<NW>::BN * 68; }
+template <int NW>
+constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
+
+template <int PREC, int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
+    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
+    float tau, float* __restrict__ ubound) {
+  constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
+  constexpr int HD_PIPE = HdShape<NW>::PIPE;
+  constexpr int NT = 64 * NW;
+  constexpr int SQ = 256 * 64, SR = BN * 64, STG = (int)hd_stage_bytes<NW>();
+  constexpr int NLQ = 1024 / NT, NLR = BN * 4 / NT;   // 16-byte query / row chunks per thread
+  constexpr int NLD = NLQ + NLR + 1;                  // loads per thread per stage (+ one norm)
+  using LS = typename ListRegs<QW>::S;
+  using LJ = typename ListRegs<QW>::J;
+  const char* Xb = reinterpret_cast<const char*>(Xq_);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;
+  const int nks = RS >> 6;   // K-steps per row
+
+  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
+  float nql, bcl0, bcl1, U[QB];
+  {
+    const int q = wq0 + lane;
+    const bool ok = lane < QW && q < bd.q1;
+    nql = ok ? nq[q] : 0.f;
+    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
+  }
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) U[qb] = (wq0 + qb * 16 + i16 < bd.q1) ? F_INF : -F_INF;
+  LS ls;
+  LJ lj;
+#pragma unroll
+  for (int L = 0; L < QW / 2; ++L) {
+    ls[L] = F_INF;
+    lj[L] = 0x7FFFFFFF;
+  }
+
+  // this thread's source offsets within the staged query block and row tile
+  // (the copy holds 256 padding rows past its end: no clamps)
+  unsigned qoff[NLQ], roff[NLR];
+#pragma unroll
+  for (int i = 0; i < NLQ; ++i) {
+    const int p = tid + NT * i, r = p >> 2;
+    qoff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+  }
+#pragma unroll
+  for (int i = 0; i < NLR; ++i) {
+    const int p = tid + NT * i, r = p >> 2;
+    roff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+  }
+  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
+  const char* qbase = Xb + (int64_t)bd.q0 * RS;
+  int lt = 0, lk = 0;   // tile and K-step of the next stage to load
+  auto issue = [&](int stg) {
+    const int t0 = bd.c0 + lt * BN;
+    const int kofs = lk * 64;
+    if (++lk == nks) {
+      lk = 0;
+      lt = lt + 1 == ntile ? 0 : lt + 1;
+    }
+    char* stage = smem + stg * STG;
+    const char* qb_ = qbase + kofs;
+    const char* rb_ = Xb + (int64_t)t0 * RS + kofs;
+#pragma unroll
+    for (int i = 0; i < NLQ; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(qb_ + qoff[i]), (lptr_t)(stage + (NT * i + 64 * wave) * 16),
+                                       16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NLR; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(rb_ + roff[i]),
+                                       (lptr_t)(stage + SQ + (NT * i + 64 * wave) * 16), 16, 0, 0);
+    // the BN norms: wave w fetches norms 64 (w mod BN/64) .. + 63 (duplicates write equal values)
+    const int nw = wave & (BN / 64 - 1);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + nw * 64 + lane),
+                                     (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
+  };
+
+  f32x4 acc[QB][JB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
+  const int nst = ntile * nks;
+  int cs = 0, ct = 0, ck = 0;   // stage slot, tile and K-step being computed
+  for (int st = 0; st < nst; ++st) {
+    wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
+    __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
+    issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
+    const char* stage = smem + cs * STG;
+    // query fragments of this wave (B) and row fragments (A), one K-step
+    i32x4 bq[QB];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int r = wave * QW + qb * 16 + i16;
+      bq[qb] = *reinterpret_cast<const i32x4*>(stage + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+    }
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      const int r = jb * 16 + i16;
+      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        if constexpr (PREC == FAMST_FP32) {
+          const f32x4 af = __builtin_bit_cast(f32x4, a);
+          const f32x4 bf = __builtin_bit_cast(f32x4, bq[qb]);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
+        } else {
+          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bq[qb]), acc[qb][jb], 0, 0, 0);
+        }
+      }
+    }
+    if (++ck == nks) {
+      // tile complete: screened value |y|^2 - 2 x.y, filter and insertion in
+      // groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
+      const int t0 = bd.c0 + ct * BN;
+      const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
+#pragma unroll
+      for (int h = 0; h < JB / 2; ++h) {
+        float nqj[2][4];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * h + jj) * 16 + 4 * g);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
+        }
+        unsigned qbmask = 0;
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          float m = F_INF;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            m = fminf(m, __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]));
+          qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+        }
+        if (qbmask)
+          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
+                             [&](int qb, int e) {
+                               return __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
+                             },
+                             t0 + 32 * h, bd.c1, wq0, lane, g, i16);
+      }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ck = 0;
+      ++ct;
+    }
+    cs = cs + 1 == HD_PIPE ? 0 : cs + 1;
+  }
+  wait_vmcnt<0>();   // no load may land in LDS after the block ends
+
+  float nqv[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
+  if (g == 0) {
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int q = wq0 + qb * 16 + i16;
+      if (q < bd.q1) ubound[q] = U[qb] + nqv[qb];
+    }
+  }
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int L = 0; L < QW / 2; ++L) {
+    const int q = wq0 + 2 * L + half;
+    if (q < bd.q1) {
+      cand_s[(int64_t)q * KC + rel] = ls[L];
+      cand_j[(int64_t)q * KC + rel] = lj[L];
+    }
+  }
+}
+
+}  // namespace famst

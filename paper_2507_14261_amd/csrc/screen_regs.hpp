@@ -1,0 +1,174 @@
+// Screening work units, candidate records and the register-list machinery shared by the pipelined screening kernels.
+#pragma once
+#include "famst_common.hpp"
+
+namespace famst {
+
+// ------------------------------------------------------ distance + top-k'
+// Work unit of one block: queries [q0, q1) of one cloud against the
+// cloud's rows [c0, c1).
+struct BlockDesc {
+  int q0, q1, c0, c1;
+};
+
+struct __attribute__((aligned(8))) Cand {
+  float s;
+  int j;
+};
+
+template <int PREC>
+struct Scr;
+template <>
+struct Scr<FAMST_FP32> {
+  using T = float;
+  static constexpr int KBW = 16;  // k covered by one 16-byte fragment per lane x 4 lane groups
+  static constexpr int ESZ = 4;
+};
+template <>
+struct Scr<FAMST_BF16> {
+  using T = uint16_t;
+  static constexpr int KBW = 32;
+  static constexpr int ESZ = 2;
+};
+
+// ------------------------------------------- pipelined screening, k' = 32
+// The products, filter and insertion rule of dist_topk_kernel, organised
+// for memory-level parallelism: the per-query lists live in registers,
+// which frees LDS for a ring of PIPE tile stages filled by direct
+// global->LDS loads, so PIPE-1 tiles are in flight while one is consumed and
+// a single barrier per tile suffices.
+//
+// Register lists: query qi (0..63) of a wave owns register pair qi/2 of
+// (ls, lj), lanes 32 (qi & 1) .. 32 (qi & 1) + 31, ascending by (s, j).
+typedef float f32x32 __attribute__((ext_vector_type(32)));
+typedef int i32x32 __attribute__((ext_vector_type(32)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+typedef int i32x16v __attribute__((ext_vector_type(16)));
+// register lists of a wave with QW queries: QW / 2 register pairs
+template <int QW> struct ListRegs;
+template <> struct ListRegs<64> { using S = f32x32; using J = i32x32; };
+template <> struct ListRegs<32> { using S = f32x16v; using J = i32x16v; };
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+constexpr int PIPE = 4;
+static_assert((PIPE & (PIPE - 1)) == 0, "stage index by mask");
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  // gfx9 s_waitcnt: vmcnt in bits [3:0] and [15:14]; expcnt and lgkmcnt at
+  // their maxima (not waited for)
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Screening band above the k-th screened value T of a query: wide enough
+// that the re-rank certificate (screening arithmetic error eps, input
+// rounding e = e_q + e_max, float32 near-tie factor tau) holds for every
+// element the filter rejects:
+//   band(T) = (2 eps + 4 e^2) + 4 e sqrt(T) + (8 tau + 1e-5) |T|,
+// +inf while fewer than k entries exist.  Only the chance of certifying
+// depends on it: the certificate itself uses the final threshold, which
+// bounds every rejected element whatever the band was.
+struct Band {
+  float arith_c, nmax, emax, tau;
+  // per-query constants: c0 = 2 eps + 4 e^2, c1 = 4 e
+  __device__ __forceinline__ void consts(float nqv, float eqv, float& c0, float& c1) const {
+    const float e = eqv + emax;
+    c0 = 2.f * arith_c * (nqv + nmax) + 4.f * e * e;
+    c1 = 4.f * e;
+  }
+  __device__ __forceinline__ float operator()(float Tk, float c0, float c1) const {
+    if (!(Tk < F_INF)) return F_INF;
+    // hardware square root, rounded up by a few ulps
+    const float r = c1 > 0.f ? __builtin_amdgcn_sqrtf(fmaxf(Tk, 0.f)) * 1.000001f : 0.f;
+    return c0 + c1 * r + (8.f * tau + 1e-5f) * fabsf(Tk);
+  }
+};
+
+// The filter threshold of a query is U = T_k - |x_q|^2 + band(T_k) with T_k
+// the k-th entry of its list (not the last): an element screened above it
+// cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
+// rejected element for the certificate.
+//
+// Elements are taken element-major: for each of the NE elements a lane
+// holds (a static register), a ballot gives the lanes whose element passed,
+// and each is inserted in turn into its query's list (a ballot gives the
+// position, DPP wave_shr:1 shifts the tail, the query's threshold follows
+// the new k-th entry).
+template <int QB, int NE, class LS, class LJ, class SpFn>
+__device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB],
+                                            float nql, float bcl0, float bcl1,
+                                            const Band& band, int kk,
+                                            SpFn spf, int t0, int c1, int wq0, int lane, int g,
+                                            int i16) {
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    if (!(qbmask & (1u << qb))) continue;
+    const int q = wq0 + qb * 16 + i16;
+    float sp[NE];
+    bool ok[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      sp[e] = spf(qb, e);
+      const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
+      ok[e] = (sp[e] <= U[qb]) & (j < c1) & (j != q);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      unsigned long long lanes = ballot(ok[e]);
+      while (lanes) {
+        const int src = __builtin_ctzll(lanes);
+        lanes &= lanes - 1;
+        const float spv = readlane_f(sp[e], src);
+        if (!(spv <= readlane_f(U[qb], src))) continue;   // list tightened meanwhile
+        const int qi = qb * 16 + (src & 15);
+        const int L = qi >> 1, h = qi & 1;
+        const int j = t0 + (e >> 2) * 16 + 4 * (src >> 4) + (e & 3);
+        const int qw = qb * 16 + (src & 15);   // query within the wave
+        const float nqv = readlane_f(nql, qw);
+        const float s = spv + nqv;
+        const float cs = ls[L];
+        const int cjv = lj[L];
+        const bool mine = half == h;
+        const bool lt = mine & ((cs < s) | ((cs == s) & (cjv < j)));
+        const int pos = __builtin_popcountll(ballot(lt));
+        if (pos >= 32) continue;
+        // shift the tail of the half up by one (DPP wave_shr:1); the first
+        // lane of a half never takes the shifted value
+        const float ups = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(cs), 0x138, 0xF, 0xF, false));
+        const int upj = __builtin_amdgcn_update_dpp(0, cjv, 0x138, 0xF, 0xF, false);
+        const bool keep = !mine | (rel < pos);
+        const float ns = keep ? cs : (rel == pos ? s : ups);
+        const int nj = keep ? cjv : (rel == pos ? j : upj);
+        ls[L] = ns;
+        lj[L] = nj;
+        const float Tk = readlane_f(ns, 32 * h + kk - 1);
+        const float Un = (Tk - nqv) + band(Tk, readlane_f(bcl0, qw), readlane_f(bcl1, qw));
+        U[qb] = (i16 == (src & 15)) ? Un : U[qb];
+      }
+    }
+  }
+}
+
+// A query fragment (8 bf16 or 4 float32 values) times -2; exact for every
+// finite input (a power-of-two scaling, far from overflow for rows that
+// passed the norm check).
+template <int PREC>
+__device__ __forceinline__ i32x4 neg2_fragment(i32x4 v) {
+  if constexpr (PREC == FAMST_FP32) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = __float_as_int(-2.f * __int_as_float(v[i]));
+    return v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned u = (unsigned)v[i];
+      const unsigned lo = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u & 0xFFFFu)));
+      const unsigned hi = f32_to_bf16_rne(-2.f * bf16_to_f32((uint16_t)(u >> 16)));
+      v[i] = (int)(lo | (hi << 16));
+    }
+    return v;
+  }
+}
+
+}  // namespace famst

@@ -1,0 +1,219 @@
+// Pipelined screening with register-resident queries (k' = 32, up to 128 bf16 / 64 fp32 dims).
+#pragma once
+#include "screen_regs.hpp"
+
+namespace famst {
+
+template <int PREC, int NKB>
+__global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
+    const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
+    const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
+    int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
+    float tau, float* __restrict__ ubound, const int* __restrict__ perm) {
+  using S = Scr<PREC>;
+  constexpr int QB = 4, KC = 32, QW = 64, BN = 64;
+  constexpr int TILE = BN * NKB * 64;   // 64 rows x NKB 64-byte chunks
+  constexpr int STG = TILE + 256;       // tile + its 64 norms
+  const char* Xb = reinterpret_cast<const char*>(Xq_);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+
+  const BlockDesc bd = desc[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, i16 = lane & 15;
+  const int wq0 = bd.q0 + wave * QW;
+  // instantiated for the exact number of K-blocks: no runtime guards in the
+  // tile loop (they would split it into branches and force full waits)
+  constexpr int RS = NKB * 64, cpr = NKB * 4;
+  constexpr int smask = (cpr & 15) == 0 ? 15 : ((cpr & 7) == 0 ? 7 : 3);
+
+  // resident query fragments, scaled by -2 (exact): the products then
+  // accumulate onto the row norms and yield the screened value
+  // |y|^2 - 2 x.y directly.  The norm and the band constants of the wave's
+  // query l sit in lane l (only insertions read them, by readlane).
+  i32x4 qf[QB][NKB];
+  float U[QB];
+  const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
+  float nql, bcl0, bcl1;
+  {
+    const int q = wq0 + lane;
+    const bool ok = q < bd.q1;
+    nql = ok ? nq[q] : 0.f;
+    band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
+  }
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = wq0 + qb * 16 + i16;
+    const bool ok = q < bd.q1;
+    U[qb] = ok ? F_INF : -F_INF;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      i32x4 v = {0, 0, 0, 0};
+      if (ok) v = *reinterpret_cast<const i32x4*>(Xb + (int64_t)q * RS + kb * 64 + g * 16);
+      qf[qb][kb] = neg2_fragment<PREC>(v);
+    }
+  }
+  f32x32 ls;
+  i32x32 lj;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    ls[L] = F_INF;
+    lj[L] = 0x7FFFFFFF;
+  }
+
+  // Loads of a tile into a stage: chunk slot p of the stage holds chunk
+  // (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
+  // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
+  // its slot; its byte offset from the tile's first row is the same for
+  // every tile.  The screening copy and its norms hold 64 padding rows past
+  // the last cloud, so a tile never reads outside them (rows past a cloud
+  // never enter a list).  Every thread issues NKB + 1 loads per tile, which
+  // keeps the vmcnt bookkeeping static.
+  // Scan order: tiles tstart, tstart + 1, ... cyclically.  With a spatial
+  // order (perm != null: rows of Xq are the points perm[.], grouped by
+  // nearest pivot) tstart is the tile of the block's own first query, so the
+  // likely neighbours come first and the thresholds tighten early.  Two
+  // scalar counters follow the tile to load and the tile to compute.
+  const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
+  const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
+  int tl = tstart;   // next tile to load
+  unsigned voff[NKB];
+#pragma unroll
+  for (int i = 0; i < NKB; ++i) {
+    const int p = tid + 256 * i;
+    const int r = p / cpr, sc = p - r * cpr;
+    voff[i] = (unsigned)(r * RS + ((sc ^ (r & smask)) << 4));
+  }
+  auto issue = [&](int stg) {
+    const int t0 = bd.c0 + tl * BN;
+    tl = tl + 1 == ntile ? 0 : tl + 1;
+    char* stage = smem + stg * STG;
+    const char* tb = Xb + (int64_t)t0 * RS;
+#pragma unroll
+    for (int i = 0; i < NKB; ++i)
+      __builtin_amdgcn_global_load_lds((gptr_t)(tb + voff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
+                                       16, 0, 0);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + lane), (lptr_t)(stage + TILE), 4, 0, 0);
+  };
+  // one tile consumed by every thread: wait for the next tile's loads, let
+  // every wave pass, and refill the stage the consumed tile used
+  auto next_tile = [&](int it) {
+    wait_vmcnt<(PIPE - 2) * (NKB + 1)>();   // this thread's loads of tile it are done
+    __builtin_amdgcn_s_barrier();           // ... and every thread's; tile it-1 is consumed
+    issue((it + PIPE - 1) & (PIPE - 1));    // into the stage tile it-1 used
+  };
+
+  // Products of one half (32 rows) of a tile: the accumulators start at the
+  // norms of their rows; A fragments double-buffered (the LDS reads of
+  // K-step kb + 1 are issued before the products of K-step kb).
+  auto products = [&](const char* tile, int jh, f32x4 (&acc)[QB][2]) {
+    const float* tn = reinterpret_cast<const float*>(tile + TILE);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * jh + jj) * 16 + 4 * g);
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) acc[qb][jj] = v;
+    }
+    auto lda = [&](int kb, i32x4 (&a)[2]) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int r = (2 * jh + jj) * 16 + i16;
+        const int cc = kb * 4 + g;
+        a[jj] = *reinterpret_cast<const i32x4*>(tile + r * RS + ((cc ^ (r & smask)) << 4));
+      }
+    };
+    i32x4 acur[2], anxt[2];
+    lda(0, acur);
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb + 1 < NKB) lda(kb + 1, anxt);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const i32x4 a = acur[jj];
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          if constexpr (PREC == FAMST_FP32) {
+            const f32x4 af = __builtin_bit_cast(f32x4, a);
+            const f32x4 bf = __builtin_bit_cast(f32x4, qf[qb][kb]);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jj], 0, 0, 0);
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jj], 0, 0, 0);
+          } else {
+            acc[qb][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, qf[qb][kb]), acc[qb][jj], 0, 0, 0);
+          }
+        }
+      }
+      if (kb + 1 < NKB) {
+        acur[0] = anxt[0];
+        acur[1] = anxt[1];
+      }
+    }
+  };
+  // Screening filter of one half: lane holds rows t0h + jj*16 + 4g + r,
+  // query qb*16 + i16.
+  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h) {
+    unsigned qbmask = 0;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      float m = acc[qb][0][0];
+#pragma unroll
+      for (int e = 1; e < 8; ++e) m = fminf(m, acc[qb][e >> 2][e & 3]);
+      qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+    }
+    if (qbmask)
+      insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
+                         [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; },
+                         t0h, bd.c1, wq0, lane, g, i16);
+  };
+
+  // Software pipeline over halves: the products of the next half are issued
+  // before the filter (and any insertion) of the current one, so the matrix
+  // cores stay busy meanwhile.
+#pragma unroll
+  for (int it = 0; it < PIPE - 1; ++it) issue(it);
+  f32x4 accA[QB][2], accB[QB][2];
+  next_tile(0);
+  products(smem, 0, accA);
+  int tc = tstart;   // tile being computed
+  for (int it = 0; it < ntile; ++it) {
+    const char* tile = smem + (it & (PIPE - 1)) * STG;
+    const int t0 = bd.c0 + tc * BN;
+    tc = tc + 1 == ntile ? 0 : tc + 1;
+    products(tile, 1, accB);
+    filter(accA, t0);
+    if (it + 1 < ntile) {
+      next_tile(it + 1);
+      products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
+    }
+    filter(accB, t0 + 32);
+  }
+  wait_vmcnt<0>();   // no load may land in LDS after the block ends
+
+  // ---- write the candidate lists and the bound of the rejected elements
+  // (rows and ids back in the caller's numbering under a spatial order)
+  float nqv[QB];   // norms of the lane's queries (every lane takes part in the shuffles)
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) nqv[qb] = __shfl(nql, qb * 16 + i16);
+  if (g == 0) {
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const int q = wq0 + qb * 16 + i16;
+      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqv[qb];
+    }
+  }
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int L = 0; L < 32; ++L) {
+    const int q = wq0 + 2 * L + half;
+    if (q < bd.q1) {
+      const int qo = perm ? perm[q] : q;
+      const int jv = lj[L];
+      cand_s[(int64_t)qo * KC + rel] = ls[L];
+      cand_j[(int64_t)qo * KC + rel] = (perm && jv != 0x7FFFFFFF) ? perm[jv] : jv;
+    }
+  }
+}
+
+}  // namespace famst
