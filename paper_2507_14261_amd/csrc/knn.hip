@@ -907,7 +907,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   // beyond the register-resident queries (and for float32 beyond 64 dims,
   // where the streamed operands cost less than the LDS-list kernel's waits)
   if (prec != FAMST_FP8_E4M3 && p.KC == 32 && (d > 128 || (prec == FAMST_FP32 && d > 64))) {
-    const int kdim = 64 / p.esz;   // dimensions per 64-byte K-step
+    const int kdim = (prec == FAMST_FP32 ? HdShape<4>::KSB : HdShape<8>::KSB) / p.esz;   // dims per stage
     p.chunked = false;
     p.hd = true;
     p.DP = (d + kdim - 1) / kdim * kdim;

@@ -25,10 +25,12 @@ namespace famst {
 // float32, four times slower per byte on the matrix cores, takes 256 x 128
 // with two blocks per CU and three stages.
 template <int NW> struct HdShape;
-template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3; };
-template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 4; };
+template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3, KSB = 64; };
+template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 2, KSB = 128; };
 template <int NW>
-constexpr size_t hd_stage_bytes() { return (size_t)256 * 64 + (size_t)HdShape<NW>::BN * 68; }
+constexpr size_t hd_stage_bytes() {
+  return (size_t)256 * HdShape<NW>::KSB + (size_t)HdShape<NW>::BN * (HdShape<NW>::KSB + 4);
+}
 template <int NW>
 constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
 
@@ -39,10 +41,14 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
     float tau, float* __restrict__ ubound) {
   constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
-  constexpr int HD_PIPE = HdShape<NW>::PIPE;
+  constexpr int HD_PIPE = HdShape<NW>::PIPE, KSB = HdShape<NW>::KSB;
+  constexpr int CPR = KSB / 16, KX = KSB / 64;   // 16-byte chunks per staged row; MFMA K-steps per stage
+  // chunk c of staged row r sits at slot c ^ swz(r): eight consecutive rows
+  // then cover all 32 banks for 64-byte and for 128-byte rows
+  auto swz = [](int r) { return CPR == 4 ? ((r >> 1) & 3) : (r & 7); };
   constexpr int NT = 64 * NW;
-  constexpr int SQ = 256 * 64, SR = BN * 64, STG = (int)hd_stage_bytes<NW>();
-  constexpr int NLQ = 1024 / NT, NLR = BN * 4 / NT;   // 16-byte query / row chunks per thread
+  constexpr int SQ = 256 * KSB, SR = BN * KSB, STG = (int)hd_stage_bytes<NW>();
+  constexpr int NLQ = 256 * CPR / NT, NLR = BN * CPR / NT;   // 16-byte query / row chunks per thread
   constexpr int NLD = NLQ + NLR + 1;                  // loads per thread per stage (+ one norm)
   using LS = typename ListRegs<QW>::S;
   using LJ = typename ListRegs<QW>::J;
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, i16 = lane & 15;
   const int wq0 = bd.q0 + wave * QW;
-  const int nks = RS >> 6;   // K-steps per row
+  const int nks = RS / KSB;   // stages per row
 
   const Band band{arith_c, __uint_as_float(gstat[1]), __uint_as_float(gstat[2]), tau};
   float nql, bcl0, bcl1, U[QB];
@@ -79,20 +85,20 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
   unsigned qoff[NLQ], roff[NLR];
 #pragma unroll
   for (int i = 0; i < NLQ; ++i) {
-    const int p = tid + NT * i, r = p >> 2;
-    qoff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+    const int p = tid + NT * i, r = p / CPR;
+    qoff[i] = (unsigned)(r * RS + (((p % CPR) ^ swz(r)) << 4));
   }
 #pragma unroll
   for (int i = 0; i < NLR; ++i) {
-    const int p = tid + NT * i, r = p >> 2;
-    roff[i] = (unsigned)(r * RS + (((p & 3) ^ ((r >> 1) & 3)) << 4));
+    const int p = tid + NT * i, r = p / CPR;
+    roff[i] = (unsigned)(r * RS + (((p % CPR) ^ swz(r)) << 4));
   }
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
   const char* qbase = Xb + (int64_t)bd.q0 * RS;
   int lt = 0, lk = 0;   // tile and K-step of the next stage to load
   auto issue = [&](int stg) {
     const int t0 = bd.c0 + lt * BN;
-    const int kofs = lk * 64;
+    const int kofs = lk * KSB;
     if (++lk == nks) {
       lk = 0;
       lt = lt + 1 == ntile ? 0 : lt + 1;
@@ -129,29 +135,33 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
     issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
     const char* stage = smem + cs * STG;
-    // query fragments of this wave (B) and row fragments (A), one K-step
-    i32x4 bq[QB];
+    // query fragments of this wave (B) and row fragments (A), KX K-steps
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      const int r = wave * QW + qb * 16 + i16;
-      bq[qb] = *reinterpret_cast<const i32x4*>(stage + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
-    }
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) {
-      const int r = jb * 16 + i16;
-      const i32x4 a = *reinterpret_cast<const i32x4*>(stage + SQ + r * 64 + ((g ^ ((r >> 1) & 3)) << 4));
+    for (int kx = 0; kx < KX; ++kx) {
+      const int cc = kx * 4 + g;
+      i32x4 bq[QB];
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
-        if constexpr (PREC == FAMST_FP32) {
-          const f32x4 af = __builtin_bit_cast(f32x4, a);
-          const f32x4 bf = __builtin_bit_cast(f32x4, bq[qb]);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
-        } else {
-          acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bq[qb]), acc[qb][jb], 0, 0, 0);
+        const int r = wave * QW + qb * 16 + i16;
+        bq[qb] = *reinterpret_cast<const i32x4*>(stage + r * KSB + ((cc ^ swz(r)) << 4));
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int r = jb * 16 + i16;
+        const i32x4 a = *reinterpret_cast<const i32x4*>(stage + SQ + r * KSB + ((cc ^ swz(r)) << 4));
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+          if constexpr (PREC == FAMST_FP32) {
+            const f32x4 af = __builtin_bit_cast(f32x4, a);
+            const f32x4 bf = __builtin_bit_cast(f32x4, bq[qb]);
+            acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[0], acc[qb][jb], 0, 0, 0);
+            acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[1], acc[qb][jb], 0, 0, 0);
+            acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[2], acc[qb][jb], 0, 0, 0);
+            acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[3], bf[3], acc[qb][jb], 0, 0, 0);
+          } else {
+            acc[qb][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bq[qb]), acc[qb][jb], 0, 0, 0);
+          }
         }
       }
     }
