@@ -904,9 +904,10 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
   p.piped = false;
   p.hd = false;
-  // beyond the register-resident queries (and for float32 beyond 64 dims,
-  // where the streamed operands cost less than the LDS-list kernel's waits)
-  if (prec != FAMST_FP8_E4M3 && p.KC == 32 && (d > 128 || (prec == FAMST_FP32 && d > 64))) {
+  // beyond the register-resident queries (for float32 beyond 64 dims, where
+  // the streamed operands cost less than the LDS-list kernel's waits; for
+  // float8 at any d)
+  if (p.KC == 32 && (prec == FAMST_FP8_E4M3 || d > 128 || (prec == FAMST_FP32 && d > 64))) {
     const int kdim = (prec == FAMST_FP32 ? HdShape<4>::KSB : HdShape<8>::KSB) / p.esz;   // dims per stage
     p.chunked = false;
     p.hd = true;
@@ -999,7 +1000,7 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
 
 template <int PREC, int NW>
 static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
-                     const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
+                     const float* scl, const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
   auto kern = dist_topk_hd_kernel<PREC, NW>;
   static bool attr = false;
   if (!attr) {
@@ -1008,7 +1009,7 @@ static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), hd_lds_bytes<NW>(), s, Xq, nq,
-                p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound);
+                p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, scl);
 }
 
 template <int PREC>
@@ -1113,7 +1114,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   // block reads of the pipelined kernels run up to 255 rows past a cloud)
   void* Xq = cv.take<char>((size_t)(n + 256) * p.DP * esz);
   float* nq = cv.take<float>(n + 256);
-  float* scl = cv.take<float>(n);
+  float* scl = cv.take<float>(n + 256);   // float8 row scales (+ padding, as the norms)
   float* qerr = cv.take<float>(n);
   unsigned* gstat = cv.take<unsigned>(4);
   BlockDesc* desc = cv.take<BlockDesc>(nblk);
@@ -1158,11 +1159,12 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e6 = hipMemsetAsync(ovf, 0, sizeof(int), s);
   hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)256 * p.DP * esz, s);
   hipError_t e8 = hipMemsetAsync(nq + n, 0, 256 * sizeof(float), s);
+  hipError_t e11 = hipMemsetAsync(scl + n, 0, 256 * sizeof(float), s);
   hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)256 * p.DP * esz, s) : hipSuccess;
   hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
-  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10) return FAMST_EHIP;
+  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11) return FAMST_EHIP;
 
   const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
   if (prec == FAMST_FP32)
@@ -1195,8 +1197,9 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
   else if (p.hd)
-    FAMST_TRY((prec == FAMST_FP32 ? launch_hd<FAMST_FP32, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba)
-                                  : launch_hd<FAMST_BF16, 8>(p, nblk, s, Xq, nq, desc, cj, cs, ba)));
+    FAMST_TRY((prec == FAMST_FP32   ? launch_hd<FAMST_FP32, 4>(p, nblk, s, Xq, nq, nullptr, desc, cj, cs, ba)
+               : prec == FAMST_BF16 ? launch_hd<FAMST_BF16, 8>(p, nblk, s, Xq, nq, nullptr, desc, cj, cs, ba)
+                                    : launch_hd<FAMST_FP8_E4M3, 8>(p, nblk, s, Xq, nq, scl, desc, cj, cs, ba)));
   else if (prec == FAMST_FP32)
     FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
   else

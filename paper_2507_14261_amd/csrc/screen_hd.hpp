@@ -29,7 +29,9 @@ template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3,
 template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 2, KSB = 128; };
 template <int NW>
 constexpr size_t hd_stage_bytes() {
-  return (size_t)256 * HdShape<NW>::KSB + (size_t)HdShape<NW>::BN * (HdShape<NW>::KSB + 4);
+  // query rows, tile rows, the tile's norms (and, in the 8-wave shape, the
+  // tile's float8 row scales)
+  return (size_t)256 * HdShape<NW>::KSB + (size_t)HdShape<NW>::BN * (HdShape<NW>::KSB + (NW == 8 ? 8 : 4));
 }
 template <int NW>
 constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
@@ -39,8 +41,10 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
-    float tau, float* __restrict__ ubound) {
+    float tau, float* __restrict__ ubound, const float* __restrict__ scl) {
   constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
+  constexpr bool F8 = PREC == FAMST_FP8_E4M3;   // per-row scales: s = |y|^2 - 2 a_x a_y codes.codes
+  static_assert(!F8 || (NW == 8 && HdShape<NW>::KSB == 128), "float8: one 128-dim K-step per stage");
   constexpr int HD_PIPE = HdShape<NW>::PIPE, KSB = HdShape<NW>::KSB;
   constexpr int CPR = KSB / 16, KX = KSB / 64;   // 16-byte chunks per staged row; MFMA K-steps per stage
   // chunk c of staged row r sits at slot c ^ swz(r): eight consecutive rows
@@ -70,8 +74,13 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     nql = ok ? nq[q] : 0.f;
     band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
   }
+  float aq[QB];   // float8 scales of the lane's queries (1 otherwise)
 #pragma unroll
-  for (int qb = 0; qb < QB; ++qb) U[qb] = (wq0 + qb * 16 + i16 < bd.q1) ? F_INF : -F_INF;
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = wq0 + qb * 16 + i16;
+    U[qb] = q < bd.q1 ? F_INF : -F_INF;
+    aq[qb] = (F8 && q < bd.q1) ? scl[q] : 1.f;
+  }
   LS ls;
   LJ lj;
 #pragma unroll
@@ -114,10 +123,15 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     for (int i = 0; i < NLR; ++i)
       __builtin_amdgcn_global_load_lds((gptr_t)(rb_ + roff[i]),
                                        (lptr_t)(stage + SQ + (NT * i + 64 * wave) * 16), 16, 0, 0);
-    // the BN norms: wave w fetches norms 64 (w mod BN/64) .. + 63 (duplicates write equal values)
+    // the BN norms: wave w fetches norms 64 (w mod BN/64) .. + 63 (duplicates write equal values);
+    // with float8 the second half of the waves fetches the row scales instead
     const int nw = wave & (BN / 64 - 1);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + nw * 64 + lane),
-                                     (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
+    if (F8 && wave >= BN / 64)
+      __builtin_amdgcn_global_load_lds((gptr_t)(scl + t0 + nw * 64 + lane),
+                                       (lptr_t)(stage + SQ + SR + BN * 4 + nw * 256), 4, 0, 0);
+    else
+      __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + nw * 64 + lane),
+                                       (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
   };
 
   f32x4 acc[QB][JB];
@@ -135,9 +149,32 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
     issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
     const char* stage = smem + cs * STG;
+    if constexpr (F8) {
+      // one K-step of 128 float8 dimensions: lane (g, i16) holds 32 bytes,
+      // chunks 2g and 2g + 1 of its row
+      i32x8 bq[QB];
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb) {
+        const int r = wave * QW + qb * 16 + i16;
+        const i32x4 b0 = *reinterpret_cast<const i32x4*>(stage + r * KSB + (((2 * g) ^ swz(r)) << 4));
+        const i32x4 b1 = *reinterpret_cast<const i32x4*>(stage + r * KSB + (((2 * g + 1) ^ swz(r)) << 4));
+        bq[qb] = i32x8{b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const int r = jb * 16 + i16;
+        const i32x4 a0 = *reinterpret_cast<const i32x4*>(stage + SQ + r * KSB + (((2 * g) ^ swz(r)) << 4));
+        const i32x4 a1 = *reinterpret_cast<const i32x4*>(stage + SQ + r * KSB + (((2 * g + 1) ^ swz(r)) << 4));
+        const i32x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb)
+          acc[qb][jb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bq[qb], acc[qb][jb], 0, 0, 0,
+                                                                         127, 0, 127);
+      }
+    }
     // query fragments of this wave (B) and row fragments (A), KX K-steps
 #pragma unroll
-    for (int kx = 0; kx < KX; ++kx) {
+    for (int kx = 0; kx < (F8 ? 0 : KX); ++kx) {
       const int cc = kx * 4 + g;
       i32x4 bq[QB];
 #pragma unroll
@@ -172,28 +209,33 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
       const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
 #pragma unroll
       for (int h = 0; h < JB / 2; ++h) {
-        float nqj[2][4];
+        float nqj[2][4], cj[2][4];   // row norms and -2 (times the float8 row scale)
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
           const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * h + jj) * 16 + 4 * g);
+          f32x4 c = f32x4{1.f, 1.f, 1.f, 1.f};
+          if constexpr (F8) c = *reinterpret_cast<const f32x4*>(tn + BN + (2 * h + jj) * 16 + 4 * g);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) nqj[jj][r] = v[r];
+          for (int r = 0; r < 4; ++r) {
+            nqj[jj][r] = v[r];
+            cj[jj][r] = -2.f * c[r];
+          }
         }
+        auto sv = [&](int qb, int e) {
+          const float c = F8 ? cj[e >> 2][e & 3] * aq[qb] : -2.f;
+          return __builtin_fmaf(c, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
+        };
         unsigned qbmask = 0;
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
           float m = F_INF;
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            m = fminf(m, __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]));
+          for (int e = 0; e < 8; ++e) m = fminf(m, sv(qb, e));
           qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
         }
         if (qbmask)
-          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
-                             [&](int qb, int e) {
-                               return __builtin_fmaf(-2.f, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
-                             },
-                             t0 + 32 * h, bd.c1, wq0, lane, g, i16);
+          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0, lane,
+                             g, i16);
       }
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb)
