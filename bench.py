@@ -212,7 +212,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=1)
     ap.add_argument("--cpu-rows", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-fp32", action="store_true", help="time only the bf16-screened path")
+    ap.add_argument("--skip-fp32", action="store_true", help="do not time the float32-screened path")
+    ap.add_argument("--skip-fp8", action="store_true", help="do not time the float8-screened path")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a plain device copy of X (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -249,8 +250,15 @@ def main():
         ms_fp32, out_f, phases_f = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "fp32", True,
                                              args.fp32_steps, 1, True)
         log(f"fp32 path: {ms_fp32:.1f} ms/step")
+    if args.skip_fp8:
+        ms_fp8, out_8, phases_8 = float("nan"), None, {}
+    else:
+        ms_fp8, out_8, phases_8 = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "fp8", False,
+                                            args.fp32_steps, 1, True)
+        log(f"fp8 path: {ms_fp8:.1f} ms/step")
     Wb = float(out_b.W[0].item())
     Wf = float(out_f.W[0].item())
+    W8 = float(out_8.W[0].item()) if out_8 is not None else float("nan")
 
     # roofline of the dominant kernel (distance tiles): 2 n^2 d flops per launch
     flops = 2.0 * n * n * d
@@ -259,6 +267,8 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12 if nl else None
     nlf, totf = phases_f.get("dist_topk", {}).get("launches", 0), phases_f.get("dist_topk", {}).get("total_ms", 0.0)
     avg_f = totf / nlf if nlf else float("nan")
+    nl8, tot8 = phases_8.get("dist_topk", {}).get("launches", 0), phases_8.get("dist_topk", {}).get("total_ms", 0.0)
+    avg_8 = tot8 / nl8 if nl8 else float("nan")
 
     # achieved bandwidth of the gather / streaming kernels (algorithmic bytes)
     KC = 32 if k <= 24 else 64
@@ -292,6 +302,9 @@ def main():
         rec_b = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_b, ref_nbr)]))
         rec_f = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_f, ref_nbr)]))
         parity = {"sample_rows": int(len(rows)), "recall_bf16": rec_b, "recall_fp32": rec_f}
+        if out_8 is not None:
+            nb_8 = out_8.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
+            parity["recall_fp8"] = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_8, ref_nbr)]))
         cores = len(os.sched_getaffinity(0))
         cpu = {"value": round(len(rows) / t_cpu, 3), "unit": "points/s", "cores": cores, "kind": "oracle",
                "sample": (f"exact float64 kNN (the oracle's Phase 1, the dominant phase) of {len(rows)} "
@@ -321,7 +334,8 @@ def main():
                      "kernel": "dist_topk", "avg_ms": round(avg_ms, 3),
                      "algorithmic_flops": flops},
         "cpu_baseline": cpu,
-        "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf},
+        "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf,
+                   "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None},
         "fp32_path": None if args.skip_fp32 else {
                       "ms_per_step": round(ms_fp32, 3), "points_per_s": round(n / (ms_fp32 * 1e-3), 1),
                       "dist_topk_avg_ms": round(avg_f, 3),
@@ -330,6 +344,12 @@ def main():
         "bandwidth_bf16_path": bw,
         "phases_ms_bf16": phases_b,
         "phases_ms_fp32": phases_f,
+        "fp8_path": None if out_8 is None else {
+                     "precision": "fp8 e4m3 screening (per-row scales) + fp32 re-rank, approximate mode",
+                     "ms_per_step": round(ms_fp8, 3), "points_per_s": round(n / (ms_fp8 * 1e-3), 1),
+                     "dist_topk_avg_ms": round(avg_8, 3),
+                     "dist_topk_tflops": round(flops / (avg_8 * 1e-3) / 1e12, 2) if nl8 else None,
+                     "frac_of_fp8_peak": round(flops / (avg_8 * 1e-3) / 1e12 / PEAK_TFLOPS["fp8"], 4) if nl8 else None},
         "parity": parity,
     }
     if args.calib_copy:
