@@ -33,7 +33,7 @@ HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
         "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "1b15179f0b0498188ba34125ab07a24a815caa2e",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "b34b3ea57e914caa83962bcd9be83ac44b01e336",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 971.4, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},

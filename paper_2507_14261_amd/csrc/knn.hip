@@ -348,6 +348,9 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
 #define FAMST_NPIV 1024
 #endif
 constexpr int NPIV = FAMST_NPIV, PCH = 256;
+#ifndef FAMST_HD_SPATIAL
+#define FAMST_HD_SPATIAL 1
+#endif
 constexpr int NPIV_BITS = NPIV <= 256 ? 8 : (NPIV <= 1024 ? 10 : (NPIV <= 4096 ? 12 : 16));
 
 template <int PREC, int NKB>
@@ -449,13 +452,16 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const void* __restric
   }
 }
 
-// Permuted copies of the screening rows, norms and rounding norms.
+// Permuted copies of the screening rows, norms, rounding norms and (float8)
+// row scales (scl null: none).
 __global__ __launch_bounds__(256) void gather_rows_kernel(const char* __restrict__ Xq, int RS,
                                                           const float* __restrict__ nq,
                                                           const float* __restrict__ qerr,
+                                                          const float* __restrict__ scl,
                                                           const int* __restrict__ perm, int64_t n,
                                                           char* __restrict__ Xp, float* __restrict__ nqp,
-                                                          float* __restrict__ qerrp) {
+                                                          float* __restrict__ qerrp,
+                                                          float* __restrict__ sclp) {
   const int cpr = RS / 16;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n * cpr) return;
@@ -467,6 +473,37 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const char* __restrict
   if (sc == 0) {
     nqp[q] = nq[src];
     qerrp[q] = qerr[src];
+    if (scl) sclp[q] = scl[src];
+  }
+}
+
+// Pivot-assignment input for the streamed screening (rows of any length, any
+// precision): a 128-coordinate bf16 sketch of each row, coordinate i added
+// with sign sg(i) into slot i mod 128 (a sparse random projection; the row
+// itself for d <= 128), and the squared norm of the rounded sketch.  It only
+// decides the order in which the screening visits the rows.  One wave per row.
+__global__ __launch_bounds__(256) void sketch_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                     uint16_t* __restrict__ S, float* __restrict__ ns) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  auto sg = [d](int i, float v) {   // top bit of a multiplicative hash of i
+    return (d > 128 && ((uint32_t)i * 0x9E3779B1u) >> 31) ? -v : v;
+  };
+  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < n; row += (int64_t)gridDim.x * 4) {
+    const float* x = X + row * d;
+    float s0 = 0.f, s1 = 0.f;
+    for (int i0 = 0; i0 < d; i0 += 128) {
+      const int i = i0 + lane, j = i0 + 64 + lane;
+      if (i < d) s0 += sg(i, x[i]);
+      if (j < d) s1 += sg(j, x[j]);
+    }
+    const uint16_t b0 = f32_to_bf16_rne(s0), b1 = f32_to_bf16_rne(s1);
+    S[row * 128 + lane] = b0;
+    S[row * 128 + 64 + lane] = b1;
+    const float v0 = bf16_to_f32(b0), v1 = bf16_to_f32(b1);
+    float t = v0 * v0 + v1 * v1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) ns[row] = t;
   }
 }
 
@@ -1009,7 +1046,8 @@ static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), hd_lds_bytes<NW>(), s, Xq, nq,
-                p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, scl);
+                p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, scl,
+                ba.perm);
 }
 
 template <int PREC>
@@ -1069,15 +1107,16 @@ static int dispatch_pivots(int prec, int nkb, int64_t n, hipStream_t s, const vo
                             : pivots_prec<FAMST_BF16>(nkb, n, s, Xq, nq, key, idx);
 }
 
-// Nearest-pivot assignment, stable sort by pivot, permuted screening copy.
-static int spatial_order(int prec, int nkb, int64_t n, hipStream_t s, const void* Xq, const float* nq,
-                         const float* qerr, uint32_t* key, uint32_t* key2, int* idx, int* perm,
-                         void* tmp, size_t tmpb, char* Xp, float* nqp, float* qerrp) {
-  FAMST_TRY(dispatch_pivots(prec, nkb, n, s, Xq, nq, key, idx));
+// Nearest-pivot assignment (on rows Pq of pprec / pnkb with norms pn), stable
+// sort by pivot, permuted screening copy (rows of RS bytes).
+static int spatial_order(int pprec, int pnkb, const void* Pq, const float* pn, int64_t n, hipStream_t s,
+                         int RS, const void* Xq, const float* nq, const float* qerr, const float* scl,
+                         uint32_t* key, uint32_t* key2, int* idx, int* perm, void* tmp, size_t tmpb,
+                         char* Xp, float* nqp, float* qerrp, float* sclp) {
+  FAMST_TRY(dispatch_pivots(pprec, pnkb, n, s, Pq, pn, key, idx));
   FAMST_TRY(sort_pairs_u32_i32(tmp, tmpb, key, key2, idx, perm, (size_t)n, NPIV_BITS, s));
-  const int RS = nkb * 64;
   return launch("gather_rows", gather_rows_kernel, dim3(cdiv(n * (RS / 16), 256)), dim3(256), 0, s,
-                reinterpret_cast<const char*>(Xq), RS, nq, qerr, perm, n, Xp, nqp, qerrp);
+                reinterpret_cast<const char*>(Xq), RS, nq, qerr, scl, perm, n, Xp, nqp, qerrp, sclp);
 }
 
 }  // namespace famst
@@ -1126,9 +1165,14 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   int* bad = cv.take<int>(n);
   unsigned long long* ctr = cv.take<unsigned long long>(4);
   int* ovf = cv.take<int>(1);
-  // spatial order of the scan (one large cloud, pipelined screening)
-  const bool spatial = p.piped && B == 1 && n >= 32768;
+  // spatial order of the scan (one large cloud, pipelined or streamed
+  // screening; the streamed one assigns pivots on a 128-coordinate sketch)
+  const bool spatial = (p.piped || (p.hd && FAMST_HD_SPATIAL)) && B == 1 && n >= 32768;
   const size_t sn = spatial ? (size_t)n : 0;
+  const size_t skn = spatial && p.hd ? (size_t)n : 0;
+  uint16_t* skx = cv.take<uint16_t>(skn * 128);
+  float* sknq = cv.take<float>(skn);
+  float* sclp = cv.take<float>(skn && prec == FAMST_FP8_E4M3 ? skn + 256 : 0);
   char* Xp = cv.take<char>((sn ? sn + 256 : 0) * p.DP * esz);
   float* nqp = cv.take<float>(sn ? sn + 256 : 0);
   float* qerrp = cv.take<float>(sn);
@@ -1162,9 +1206,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e11 = hipMemsetAsync(scl + n, 0, 256 * sizeof(float), s);
   hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)256 * p.DP * esz, s) : hipSuccess;
   hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
+  hipError_t e12 = sclp ? hipMemsetAsync(sclp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
-  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11) return FAMST_EHIP;
+  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11 || e12) return FAMST_EHIP;
 
   const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
   if (prec == FAMST_FP32)
@@ -1186,9 +1231,18 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   BandArgs ba{k, qerr, gstat, arith_c, tau32(d), ub, nullptr};
   const void* Xs = Xq;
   const float* nqs = nq;
+  const float* scls = scl;
   if (spatial) {
-    FAMST_TRY(spatial_order(prec, p.nkb, n, s, Xq, nq, qerr, pkey, pkey2, pidx, perm, ptmp, ptmpb, Xp,
-                            nqp, qerrp));
+    if (p.hd) {
+      FAMST_TRY(launch("sketch", sketch_kernel, pgrid, dim3(256), 0, s, X, n, d, skx, sknq));
+      FAMST_TRY(spatial_order(FAMST_BF16, 4, skx, sknq, n, s, p.DP * esz, Xq, nq, qerr,
+                              prec == FAMST_FP8_E4M3 ? scl : nullptr, pkey, pkey2, pidx, perm, ptmp, ptmpb,
+                              Xp, nqp, qerrp, sclp));
+      if (sclp) scls = sclp;
+    } else {
+      FAMST_TRY(spatial_order(prec, p.nkb, Xq, nq, n, s, p.DP * esz, Xq, nq, qerr, nullptr, pkey, pkey2,
+                              pidx, perm, ptmp, ptmpb, Xp, nqp, qerrp, nullptr));
+    }
     Xs = Xp;
     nqs = nqp;
     ba.qerr = qerrp;
@@ -1197,9 +1251,9 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (p.chunked)
     FAMST_TRY(dispatch_kc(p, nblk, s, Xq, nq, scl, desc, cj, cs));
   else if (p.hd)
-    FAMST_TRY((prec == FAMST_FP32   ? launch_hd<FAMST_FP32, 4>(p, nblk, s, Xq, nq, nullptr, desc, cj, cs, ba)
-               : prec == FAMST_BF16 ? launch_hd<FAMST_BF16, 8>(p, nblk, s, Xq, nq, nullptr, desc, cj, cs, ba)
-                                    : launch_hd<FAMST_FP8_E4M3, 8>(p, nblk, s, Xq, nq, scl, desc, cj, cs, ba)));
+    FAMST_TRY((prec == FAMST_FP32   ? launch_hd<FAMST_FP32, 4>(p, nblk, s, Xs, nqs, nullptr, desc, cj, cs, ba)
+               : prec == FAMST_BF16 ? launch_hd<FAMST_BF16, 8>(p, nblk, s, Xs, nqs, nullptr, desc, cj, cs, ba)
+                                    : launch_hd<FAMST_FP8_E4M3, 8>(p, nblk, s, Xs, nqs, scls, desc, cj, cs, ba)));
   else if (prec == FAMST_FP32)
     FAMST_TRY(dispatch_dt<FAMST_FP32>(p, nblk, s, Xs, nqs, desc, cj, cs, ba));
   else

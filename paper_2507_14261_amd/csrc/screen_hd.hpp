@@ -6,17 +6,19 @@ namespace famst {
 
 // ------------------------------------- high-dimensional screening, k' = 32
 // For rows longer than the register-resident queries allow (more than 128
-// bf16 or 64 float32 dimensions): a block of 256 queries (the candidate
-// lists in registers as in dist_topk_v2_kernel) against tiles of rows.
-// Queries and rows both stream through LDS in K-steps of 64 bytes (32 bf16
-// or 16 float32 dimensions) by direct global->LDS loads into a ring of
-// stages; each wave accumulates its queries x tile rows over all K-steps of
-// a tile, then filters and inserts as the pipelined kernel does (same band,
-// same bound of the rejected elements).  Every block scans
-// the tiles in the same ascending order, so the blocks resident at one time
-// read the same tiles.  In a stage, 16-byte chunk c of staged row r sits at
-// slot 4 r + (c ^ ((r >> 1) & 3)): eight consecutive rows then cover all
-// LDS banks, so the operand reads are conflict-free.
+// bf16 or 64 float32 dimensions) and for float8: a block of 256 queries (the
+// candidate lists in registers as in dist_topk_v2_kernel) against tiles of
+// rows.  Queries and rows both stream through LDS in K-steps (KSB bytes) by
+// direct global->LDS loads into a ring of stages; each wave accumulates its
+// queries x tile rows over all K-steps of a tile, then filters and inserts as
+// the pipelined kernel does (same band, same bound of the rejected elements).
+// Scan order: tiles tstart, tstart + 1, ... cyclically, where tstart is 0
+// for rows in index order and, with a spatial order (perm != null: rows of
+// Xq are the points perm[.], grouped by nearest pivot), the tile of the
+// block's first query, so that the likely neighbours come first.  In a
+// stage, 16-byte chunk c of staged row r sits at slot c ^ swz(r) of the row:
+// eight consecutive rows then cover all LDS banks, so the operand reads are
+// conflict-free.
 // Block shapes: NW waves of 16 QB queries (256 queries per block) against
 // tiles of BN rows in a ring of PIPE stages; each wave accumulates
 // QB x BN / 16 fragments (128 VGPRs).  bf16 takes the square 256 x 256
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
-    float tau, float* __restrict__ ubound, const float* __restrict__ scl) {
+    float tau, float* __restrict__ ubound, const float* __restrict__ scl, const int* __restrict__ perm) {
   constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
   constexpr bool F8 = PREC == FAMST_FP8_E4M3;   // per-row scales: s = |y|^2 - 2 a_x a_y codes.codes
   static_assert(!F8 || (NW == 8 && HdShape<NW>::KSB == 128), "float8: one 128-dim K-step per stage");
@@ -104,7 +106,8 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
   }
   const int ntile = (bd.c1 - bd.c0 + BN - 1) / BN;
   const char* qbase = Xb + (int64_t)bd.q0 * RS;
-  int lt = 0, lk = 0;   // tile and K-step of the next stage to load
+  const int tstart = perm ? (bd.q0 - bd.c0) / BN : 0;
+  int lt = tstart, lk = 0;   // tile and K-step of the next stage to load
   auto issue = [&](int stg) {
     const int t0 = bd.c0 + lt * BN;
     const int kofs = lk * KSB;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
 #pragma unroll
   for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
   const int nst = ntile * nks;
-  int cs = 0, ct = 0, ck = 0;   // stage slot, tile and K-step being computed
+  int cs = 0, ct = tstart, ck = 0;   // stage slot, tile and K-step being computed
   for (int st = 0; st < nst; ++st) {
     wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
           qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
         }
         if (qbmask)
-          insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0, lane,
+          insert_regs<QB, 8, true>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0, lane,
                              g, i16);
       }
 #pragma unroll
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
       ck = 0;
-      ++ct;
+      ct = ct + 1 == ntile ? 0 : ct + 1;
     }
     cs = cs + 1 == HD_PIPE ? 0 : cs + 1;
   }
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       const int q = wq0 + qb * 16 + i16;
-      if (q < bd.q1) ubound[q] = U[qb] + nqv[qb];
+      if (q < bd.q1) ubound[perm ? perm[q] : q] = U[qb] + nqv[qb];
     }
   }
   const int half = lane >> 5, rel = lane & 31;
@@ -263,8 +266,10 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
   for (int L = 0; L < QW / 2; ++L) {
     const int q = wq0 + 2 * L + half;
     if (q < bd.q1) {
-      cand_s[(int64_t)q * KC + rel] = ls[L];
-      cand_j[(int64_t)q * KC + rel] = lj[L];
+      const int qo = perm ? perm[q] : q;
+      const int jv = lj[L];
+      cand_s[(int64_t)qo * KC + rel] = ls[L];
+      cand_j[(int64_t)qo * KC + rel] = (perm && jv != 0x7FFFFFFF) ? perm[jv] : jv;
     }
   }
 }

@@ -87,14 +87,18 @@ struct Band {
 // The filter threshold of a query is U = T_k - |x_q|^2 + band(T_k) with T_k
 // the k-th entry of its list (not the last): an element screened above it
 // cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
-// rejected element for the certificate.
+// rejected element for the certificate.  With CAPK, U is also capped at the
+// list's last entry minus |x_q|^2 (an element above it cannot enter the
+// list): where the band is wide (float8) this keeps most of the filter's
+// passes from reaching the insertion only to be dropped there; the bound
+// stays valid, as U still never increases.
 //
 // Elements are taken element-major: for each of the NE elements a lane
 // holds (a static register), a ballot gives the lanes whose element passed,
 // and each is inserted in turn into its query's list (a ballot gives the
 // position, DPP wave_shr:1 shifts the tail, the query's threshold follows
 // the new k-th entry).
-template <int QB, int NE, class LS, class LJ, class SpFn>
+template <int QB, int NE, bool CAPK = false, class LS, class LJ, class SpFn>
 __device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB],
                                             float nql, float bcl0, float bcl1,
                                             const Band& band, int kk,
@@ -143,7 +147,8 @@ __device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, flo
         ls[L] = ns;
         lj[L] = nj;
         const float Tk = readlane_f(ns, 32 * h + kk - 1);
-        const float Un = (Tk - nqv) + band(Tk, readlane_f(bcl0, qw), readlane_f(bcl1, qw));
+        float Un = (Tk - nqv) + band(Tk, readlane_f(bcl0, qw), readlane_f(bcl1, qw));
+        if constexpr (CAPK) Un = fminf(Un, readlane_f(ns, 32 * h + 31) - nqv);
         U[qb] = (i16 == (src & 15)) ? Un : U[qb];
       }
     }

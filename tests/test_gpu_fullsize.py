@@ -81,3 +81,26 @@ def test_vmf_100k_subsample_knn_recall_and_weight():
     assert rec_f == 1.0
     assert rec >= 0.99
     assert abs(float(out.W[0]) - float(ex.W[0])) / float(ex.W[0]) <= 1e-3
+
+
+def test_lowrank_500k_d960_sampled_knn_all_precisions():
+    print("case lowrank n=5e5 d=960 k=20 lambda=10", flush=True)
+    X = datagen.lowrank(n=500_000, d=960, seed=0)
+    Xd = torch.from_numpy(X).to(DEV)
+    k = 20
+    res = {}
+    for prec, exact in (("bf16", False), ("fp8", False), ("fp32", True)):
+        out = F.knn_graph(Xd, k, precision=prec, exact=exact, with_stats=True)
+        torch.cuda.synchronize()
+        res[prec] = (out[0].cpu().numpy(), out[1].cpu().numpy(), out[2])
+        print(prec, "stats", out[2], flush=True)
+    rows = _sample_rows(len(X), 32, 5)
+    ref_n, ref_s = oracle.knn_exact(X, k, rows=rows, block=16)
+    nb, ds, _ = res["fp32"]
+    for i, r in enumerate(rows):
+        assert set(nb[r].tolist()) == set(ref_n[i].tolist()), r
+    np.testing.assert_allclose(np.sort(ds[rows], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5)
+    for prec in ("bf16", "fp8"):
+        rec = oracle.recall_at_k(res[prec][0][rows], ref_n)
+        print(prec, "recall", rec, flush=True)
+        assert rec >= 0.99

@@ -186,3 +186,24 @@ def test_knn_fp8_batched_clouds():
         got = nbr[sl] - offs[b]
         for i in range(len(ref_n)):
             assert set(got[i].tolist()) == set(ref_n[i].tolist())
+
+
+# One cloud of at least 32768 points on the streamed kernel: the rows are
+# visited in a spatial order (pivots assigned on a 128-coordinate sketch),
+# and the results are mapped back to the input order.
+@pytest.mark.parametrize("prec,d", [("bf16", 200), ("fp32", 100), ("fp8", 128), ("fp8", 300)])
+def test_knn_streamed_spatial_order_sampled_rows(prec, d):
+    n, k = 40000, 10
+    print(f"case n={n} d={d} k={k} {prec} spatial order", flush=True)
+    X = datagen.blobs(n=n, d=d, n_clusters=20, seed=d + 11)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True)
+    print("stats", st, flush=True)
+    rows = np.sort(np.random.default_rng(d).choice(n, size=96, replace=False))
+    ref_n, ref_s = oracle.knn_exact(X, k, rows=rows, block=32)
+    for i, r in enumerate(rows):
+        assert set(nbr[r].tolist()) == set(ref_n[i].tolist()), (r, nbr[r], ref_n[i])
+    np.testing.assert_allclose(np.sort(dist[rows], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5, atol=1e-6)
+    assert np.all(np.diff(dist, axis=1) >= 0)
+    # every row's list holds k distinct other points
+    srt = np.sort(nbr, axis=1)
+    assert np.all(np.diff(srt, axis=1) > 0) and np.all(nbr != np.arange(n)[:, None])
