@@ -348,8 +348,14 @@ __global__ __launch_bounds__(256, (NKB <= 4 ? 2 : 1)) void dist_topk_kernel(
 #define FAMST_NPIV 1024
 #endif
 constexpr int NPIV = FAMST_NPIV, PCH = 256;
-#ifndef FAMST_HD_SPATIAL
-#define FAMST_HD_SPATIAL 1
+// The streamed screening takes the spatial order for rows of at most this
+// many bytes (0: never).  Where the filter and the insertion weigh most
+// (short rows) the early tight thresholds pay; on long rows the blocks that
+// scan the tiles in the same order share them in L2, which pays more
+// (500K x 960 bf16: 470 ms in index order, 490 ms in spatial order; 1M x
+// 128 float8: 341 ms against 262 ms).
+#ifndef FAMST_HD_SPATIAL_MAXB
+#define FAMST_HD_SPATIAL_MAXB 1024
 #endif
 constexpr int NPIV_BITS = NPIV <= 256 ? 8 : (NPIV <= 1024 ? 10 : (NPIV <= 4096 ? 12 : 16));
 
@@ -1167,12 +1173,14 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   int* ovf = cv.take<int>(1);
   // spatial order of the scan (one large cloud, pipelined or streamed
   // screening; the streamed one assigns pivots on a 128-coordinate sketch)
-  const bool spatial = (p.piped || (p.hd && FAMST_HD_SPATIAL)) && B == 1 && n >= 32768;
+  const bool spatial =
+      (p.piped || (p.hd && (int64_t)p.DP * esz <= FAMST_HD_SPATIAL_MAXB)) && B == 1 && n >= 32768;
   const size_t sn = spatial ? (size_t)n : 0;
   const size_t skn = spatial && p.hd ? (size_t)n : 0;
   uint16_t* skx = cv.take<uint16_t>(skn * 128);
   float* sknq = cv.take<float>(skn);
-  float* sclp = cv.take<float>(skn && prec == FAMST_FP8_E4M3 ? skn + 256 : 0);
+  const bool f8sp = skn && prec == FAMST_FP8_E4M3;   // permuted float8 row scales
+  float* sclp = cv.take<float>(f8sp ? skn + 256 : 0);
   char* Xp = cv.take<char>((sn ? sn + 256 : 0) * p.DP * esz);
   float* nqp = cv.take<float>(sn ? sn + 256 : 0);
   float* qerrp = cv.take<float>(sn);
@@ -1206,7 +1214,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e11 = hipMemsetAsync(scl + n, 0, 256 * sizeof(float), s);
   hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)256 * p.DP * esz, s) : hipSuccess;
   hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
-  hipError_t e12 = sclp ? hipMemsetAsync(sclp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
+  hipError_t e12 = f8sp ? hipMemsetAsync(sclp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
   if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11 || e12) return FAMST_EHIP;
@@ -1238,7 +1246,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
       FAMST_TRY(spatial_order(FAMST_BF16, 4, skx, sknq, n, s, p.DP * esz, Xq, nq, qerr,
                               prec == FAMST_FP8_E4M3 ? scl : nullptr, pkey, pkey2, pidx, perm, ptmp, ptmpb,
                               Xp, nqp, qerrp, sclp));
-      if (sclp) scls = sclp;
+      if (f8sp) scls = sclp;
     } else {
       FAMST_TRY(spatial_order(prec, p.nkb, Xq, nq, n, s, p.DP * esz, Xq, nq, qerr, nullptr, pkey, pkey2,
                               pidx, perm, ptmp, ptmpb, Xp, nqp, qerrp, nullptr));

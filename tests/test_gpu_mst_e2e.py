@@ -192,6 +192,7 @@ def test_errors():
     Xb = X.clone()
     Xb[7] = 1e19
     for prec in ("fp32", "bf16", "fp8"):
+        print("case norm overflow", prec, flush=True)
         with pytest.raises(F.FamstError) as ei:
             F.knn_graph(Xb, 3, precision=prec)
         assert ei.value.code == -6
