@@ -38,10 +38,10 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 971.4, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "ee59911332734699ff3ed07670bed014a365d06d",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "b34b3ea57e914caa83962bcd9be83ac44b01e336",
+        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "932dfef5ca9d812bbd4557204dd6ad45ccb674f5",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 1997.9, "write_GB": 0.130,
+        "fetch_GB": 2860.3, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "3a63161b4bbd18bba18885c52e54fc712cf31f6e",
