@@ -201,6 +201,22 @@ def cpu_baseline(X, k, rows):
     return nbr, t1 - t0
 
 
+def measure_peaks():
+    """Measured ceilings of this device (outside every timed region): dense
+    MFMA throughput of the three forms the screening issues (every wave of a
+    full-chip grid issuing independent MFMAs on register operands) and HBM
+    copy / read bandwidth over 1 GiB."""
+    from paper_2507_14261_amd import peaks as P
+    out = {"mfma_fp32_tflops": round(P.mfma_tflops("fp32", 200000), 1),
+           "mfma_bf16_tflops": round(P.mfma_tflops("bf16", 400000), 1),
+           "mfma_fp8_tflops": round(P.mfma_tflops("fp8", 200000), 1)}
+    c, r = P.hbm_gbps(1 << 30, 5)
+    out["hbm_copy_GBps"] = round(c, 1)
+    out["hbm_read_GBps"] = round(r, 1)
+    log(f"measured peaks: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true", help="do not time the float32-screened path")
     ap.add_argument("--skip-fp8", action="store_true", help="do not time the float8-screened path")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured MFMA / HBM ceilings")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a plain device copy of X (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -229,6 +246,12 @@ def main():
     F.load()
     if args.workload == "clouds-256-d64":
         res = bench_clouds(args, F, torch)
+        pk = None if args.no_peaks else measure_peaks()
+        res["measured_peaks"] = pk
+        rf = res["roofline"]
+        if pk and rf.get("achieved"):
+            rf["measured_peak"] = pk["hbm_read_GBps"]
+            rf["frac_of_measured"] = round(rf["achieved"] / pk["hbm_read_GBps"], 4)
         if args.calib_copy:
             calib_copy(torch)
         print(json.dumps(res), flush=True)
@@ -256,6 +279,7 @@ def main():
         ms_fp8, out_8, phases_8 = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "fp8", False,
                                             args.fp32_steps, 1, True)
         log(f"fp8 path: {ms_fp8:.1f} ms/step")
+    pk = None if args.no_peaks else measure_peaks()
     Wb = float(out_b.W[0].item())
     Wf = float(out_f.W[0].item())
     W8 = float(out_8.W[0].item()) if out_8 is not None else float("nan")
@@ -332,7 +356,10 @@ def main():
                      "frac": round(achieved / PEAK_TFLOPS["bf16"], 4) if achieved else None,
                      "traffic": measured_traffic("dist_topk", args.workload), "traffic_unit": "GB per launch",
                      "kernel": "dist_topk", "avg_ms": round(avg_ms, 3),
-                     "algorithmic_flops": flops},
+                     "algorithmic_flops": flops,
+                     "measured_peak": pk["mfma_bf16_tflops"] if pk else None,
+                     "frac_of_measured": round(achieved / pk["mfma_bf16_tflops"], 4) if pk and achieved else None},
+        "measured_peaks": pk,
         "cpu_baseline": cpu,
         "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf,
                    "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None},
@@ -340,7 +367,9 @@ def main():
                       "ms_per_step": round(ms_fp32, 3), "points_per_s": round(n / (ms_fp32 * 1e-3), 1),
                       "dist_topk_avg_ms": round(avg_f, 3),
                       "dist_topk_tflops": round(flops / (avg_f * 1e-3) / 1e12, 2) if nlf else None,
-                      "frac_of_fp32_peak": round(flops / (avg_f * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4) if nlf else None},
+                      "frac_of_fp32_peak": round(flops / (avg_f * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4) if nlf else None,
+                      "frac_of_measured_fp32": round(flops / (avg_f * 1e-3) / 1e12 / pk["mfma_fp32_tflops"], 4)
+                      if nlf and pk else None},
         "bandwidth_bf16_path": bw,
         "phases_ms_bf16": phases_b,
         "phases_ms_fp32": phases_f,
@@ -349,7 +378,9 @@ def main():
                      "ms_per_step": round(ms_fp8, 3), "points_per_s": round(n / (ms_fp8 * 1e-3), 1),
                      "dist_topk_avg_ms": round(avg_8, 3),
                      "dist_topk_tflops": round(flops / (avg_8 * 1e-3) / 1e12, 2) if nl8 else None,
-                     "frac_of_fp8_peak": round(flops / (avg_8 * 1e-3) / 1e12 / PEAK_TFLOPS["fp8"], 4) if nl8 else None},
+                     "frac_of_fp8_peak": round(flops / (avg_8 * 1e-3) / 1e12 / PEAK_TFLOPS["fp8"], 4) if nl8 else None,
+                     "frac_of_measured_fp8": round(flops / (avg_8 * 1e-3) / 1e12 / pk["mfma_fp8_tflops"], 4)
+                     if nl8 and pk else None},
         "parity": parity,
     }
     if args.calib_copy:

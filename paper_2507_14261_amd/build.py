@@ -14,6 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfamst.so")
+# measurement helpers (matrix-core and HBM ceilings), a library of their own
+PEAKS_SRC = os.path.join(CSRC, "measure", "peaks.hip")
+PEAKS_LIB = os.path.join(PKG, "libfamst_peaks.so")
 ARCH = os.environ.get("FAMST_OFFLOAD_ARCH", "gfx950")
 
 # Packed float32 instructions are disabled for the device code; the host
@@ -57,8 +60,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmp = PEAKS_LIB + ".tmp"
+    cmd = [_hipcc(), *HIPFLAGS, "-shared", PEAKS_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PEAKS_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAKS_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAKS_LIB}")
     return LIB
 
 

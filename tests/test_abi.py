@@ -79,3 +79,19 @@ def test_invalid_arguments_rejected_before_any_launch():
     assert lib.famst_mst(None, 100, 4, None, 1, None, None, 0, None, None, None, 0, 9, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
     offs = (ctypes.c_int64 * 3)(0, 1, 100)   # a one-point cloud
     assert lib.famst_mst_backward(None, 100, 4, offs, 2, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+
+
+PEAKS_HEADER = os.path.join(ROOT, "include", "famst_peaks.h")
+
+
+def test_peaks_library_exports_its_header():
+    from paper_2507_14261_amd import peaks as P
+    if not os.path.exists(P.PATH):
+        pytest.skip("libfamst_peaks.so not built")
+    txt = re.sub(r"/\*.*?\*/", "", open(PEAKS_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(famst_[a-z_0-9]+)\s*\(", txt)))
+    assert names == sorted(P.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", P.PATH], capture_output=True, text=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in names:
+        assert name in syms, name
