@@ -68,12 +68,14 @@ def measured_traffic(kernel, workload):
 WORKLOADS = {
     "gamma-int-1m-d128": ("gamma_int", dict(n=1_000_000, d=128), 20, 10),
     "blobs-10k-d32": ("blobs", dict(n=10_000, d=32), 10, 5),
+    # many components (about 1175 at k = 1): 6.9e5 component pairs, 1.7e7 lambda-samples
+    "blobs-10k-d32-k1": ("blobs", dict(n=10_000, d=32), 1, 5),
     "vmf-4m-d96": ("vmf", dict(n=4_000_000, d=96), 16, 8),
     "lowrank-500k-d960": ("lowrank", dict(n=500_000, d=960), 20, 10),
 }
 
 
-PHASES = ["prep", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan",
+PHASES = ["prep", "sketch", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan",
           "graph_keys", "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
           "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]
 

@@ -197,28 +197,31 @@ class EdgeSet:
         return EdgeSet(self.u.copy(), self.v.copy(), self.s.copy(), self.a.copy(), self.b.copy())
 
 
-def random_edges(X, comps, lam: int, seed: int, cloud: int = 0) -> EdgeSet:
+def random_edges(X, comps, lam: int, seed: int, cloud: int = 0, pairs=None) -> EdgeSet:
     """Alg. 3: for every component pair a < b draw lambda^2 endpoint pairs
     (u from C_a, v from C_b), sort them by distance (stable) and keep the
-    first lambda.  Edges are listed in (a, b, rank) order."""
+    first lambda.  Edges are listed in (a, b, rank) order.  ``pairs``
+    restricts the work to the given (a, b) pairs, in the given order: every
+    pair's draws come from its own counters, so a subset is computed exactly
+    as in the full run."""
     X64 = as64(X)
     key = seed_key(seed)
     t = len(comps)
+    if pairs is None:
+        pairs = [(a, b) for a in range(t - 1) for b in range(a + 1, t)]
     out_u, out_v, out_s, out_a, out_b = [], [], [], [], []
-    for a in range(t - 1):
-        Ca = comps[a]
-        for b in range(a + 1, t):
-            Cb = comps[b]
-            cands = []
-            for sample in range(lam * lam):
-                r = philox4x32_10((a, b, sample, cloud), key)
-                u = int(Ca[uniform_index(r[0], len(Ca))])
-                v = int(Cb[uniform_index(r[1], len(Cb))])
-                cands.append((sqdist(X64, u, v), u, v))
-            cands.sort(key=lambda c: c[0])          # stable: ties keep sample order
-            for s, u, v in cands[:lam]:
-                out_u.append(u), out_v.append(v), out_s.append(s)
-                out_a.append(a), out_b.append(b)
+    for a, b in pairs:
+        Ca, Cb = comps[a], comps[b]
+        cands = []
+        for sample in range(lam * lam):
+            r = philox4x32_10((a, b, sample, cloud), key)
+            u = int(Ca[uniform_index(r[0], len(Ca))])
+            v = int(Cb[uniform_index(r[1], len(Cb))])
+            cands.append((sqdist(X64, u, v), u, v))
+        cands.sort(key=lambda c: c[0])          # stable: ties keep sample order
+        for s, u, v in cands[:lam]:
+            out_u.append(u), out_v.append(v), out_s.append(s)
+            out_a.append(a), out_b.append(b)
     i64 = lambda x: np.array(x, dtype=np.int64)
     return EdgeSet(i64(out_u), i64(out_v), np.array(out_s, dtype=np.float64), i64(out_a), i64(out_b))
 

@@ -191,6 +191,99 @@ __global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X
   }
 }
 
+// Many edges with short neighbour rows (many components, small k): one
+// 16-lane group per edge, sixteen edges per block, each group walking the
+// neighbours of u and then of v one at a time.  Same canonical distances,
+// (s, id) order and float64 near-tie rule as refine_kernel, so the same
+// result; the round's change count takes one atomic per wave.
+constexpr int RG_EDGES = RNT / 16;
+#ifndef FAMST_REFINE_GROUP_MIN
+#define FAMST_REFINE_GROUP_MIN 32768   // edges from which the group-per-edge kernel runs
+#endif
+
+__device__ Best row_argmin_group(const float* __restrict__ X, int d, const int64_t* __restrict__ row_ptr,
+                                 const int32_t* __restrict__ col, const int32_t* __restrict__ comp,
+                                 int row, int c, int excl, int anchor, float tau, bool* used64,
+                                 double* best64, int r16) {
+  const int64_t p0 = row_ptr[row], p1 = row_ptr[row + 1];
+  const float* xa = X + (int64_t)anchor * d;
+  Best b{F_INF, 0x7FFFFFFF, F_INF};
+  for (int64_t p = p0; p < p1; ++p) {
+    const int x = col[p];
+    if (comp[x] != c || x == excl) continue;   // uniform within the group
+    best_push(b, sq32_group(X + (int64_t)x * d, xa, d, r16), x);
+  }
+  *used64 = false;
+  const float up = 1.0f + 2.0f * tau, dn = 1.0f - 2.0f * tau;
+  if (b.s1 < F_INF && b.s2 * dn <= b.s1 * up) {
+    *used64 = true;
+    double m64 = __builtin_inf();
+    int mid = 0x7FFFFFFF;
+    for (int64_t p = p0; p < p1; ++p) {
+      const int x = col[p];
+      if (comp[x] != c || x == excl) continue;
+      const float s = sq32_group(X + (int64_t)x * d, xa, d, r16);
+      if (s * dn <= b.s1 * up) {
+        const double v = sq64_group(X + (int64_t)x * d, xa, d, r16);
+        if (key_less64(v, x, m64, mid)) {
+          m64 = v;
+          mid = x;
+        }
+      }
+    }
+    b.id1 = mid;
+    b.s1 = sq32_group(X + (int64_t)mid * d, xa, d, r16);
+    *best64 = m64;
+  }
+  return b;
+}
+
+__global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restrict__ X, int d,
+                                                          const int64_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const int32_t* __restrict__ comp,
+                                                          int32_t* __restrict__ eu, int32_t* __restrict__ ev,
+                                                          float* __restrict__ ew,
+                                                          const int32_t* __restrict__ ea,
+                                                          const int32_t* __restrict__ eb, int64_t ne,
+                                                          unsigned long long* __restrict__ delta) {
+  const int r16 = threadIdx.x & 15, lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * RG_EDGES + (threadIdx.x >> 4);
+  bool changed = false;
+  if (e < ne) {
+    const float tau = tau32(d);
+    const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
+    const float* xu = X + (int64_t)u * d;
+    const float* xv = X + (int64_t)v * d;
+    float ds = sq32_group(xu, xv, d, r16);
+    int us = u, vs = v;
+    bool u64;
+    double b64 = 0.0;
+    const Best bu = row_argmin_group(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64, r16);
+    if (bu.s1 < F_INF &&
+        strictly_less(bu.s1, ds, X + (int64_t)bu.id1 * d, xv, xu, xv, d, tau, u64, b64)) {
+      us = bu.id1;
+      ds = bu.s1;
+    }
+    const float* xus = X + (int64_t)us * d;
+    const Best bv = row_argmin_group(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64, r16);
+    if (bv.s1 < F_INF &&
+        strictly_less(bv.s1, ds, xus, X + (int64_t)bv.id1 * d, xus, X + (int64_t)vs * d, d, tau, u64,
+                      b64)) {
+      vs = bv.id1;
+      ds = bv.s1;
+    }
+    changed = us != u || vs != v;
+    if (changed && r16 == 0) {
+      eu[e] = us;
+      ev[e] = vs;
+      ew[e] = __builtin_sqrtf(ds);
+    }
+  }
+  const unsigned long long m = ballot(changed && r16 == 0);
+  if (lane == 0 && m) atomicAdd(delta, (unsigned long long)__popcll(m));
+}
+
 }  // namespace famst
 
 using namespace famst;
@@ -217,8 +310,12 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   unsigned long long last = 0;
   while (r < max_rounds) {
     FAMST_HIP(hipMemsetAsync(dc, 0, sizeof(unsigned long long), s));
-    FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr,
-                     col, comp, eu, ev, ew, ea, eb, n_edges, dc));
+    if (n_edges >= FAMST_REFINE_GROUP_MIN)
+      FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(n_edges, RG_EDGES)), dim3(RNT), 0, s, X, d,
+                       row_ptr, col, comp, eu, ev, ew, ea, eb, n_edges, dc));
+    else
+      FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr,
+                       col, comp, eu, ev, ew, ea, eb, n_edges, dc));
     FAMST_HIP(hipMemcpyAsync(&last, dc, sizeof(last), hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipStreamSynchronize(s));
     if (deltas) deltas[r] = (int64_t)last;

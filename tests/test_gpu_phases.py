@@ -166,3 +166,54 @@ def test_refine_multi_round_call_and_not_converged_warning():
     assert rounds == 1 and deltas[0] > 0 and not conv
     rounds, deltas, conv = F.refine(Xd, G, E2, max_rounds=50)
     assert conv and deltas[-1] == 0 and rounds == len(deltas)
+
+
+def test_many_components_k1_sampled_pairs_and_edges():
+    # the 10,000-point blobs with k = 1: about 1175 components, 6.9e5
+    # component pairs and 1.7e7 lambda-samples.  Components are checked in
+    # full; lambda-edges on sampled pairs and refinement on sampled edges
+    # (each pair draws from its own counters, each edge refines from its own
+    # endpoints, so a sample is checked exactly).
+    n, k, lam, seed = 10_000, 1, 5, 0
+    print(f"case blobs n={n} k={k} lam={lam}", flush=True)
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=0)
+    Xd = _dev(X, torch.float32)
+    nbr, dist = F.knn_graph(Xd, k, precision="fp32", exact=True)
+    ref_nbr, _ = oracle.knn_exact(X, k)
+    assert np.array_equal(np.sort(nbr.cpu().numpy(), axis=1), np.sort(ref_nbr, axis=1))
+    G, E = F.connect(Xd, nbr, lam, seed)
+    torch.cuda.synchronize()
+    Gref = oracle.undirected_graph(ref_nbr)
+    comp_ref, comps_ref = oracle.components(Gref)
+    t = len(comps_ref)
+    print("components", t, "edges", len(E), flush=True)
+    assert t > 1000 and G.n_comp == [t]
+    assert np.array_equal(G.comp.cpu().numpy(), comp_ref)
+    u, v, w, a, b = _edges_np(E)
+    assert len(u) == lam * t * (t - 1) // 2
+    rng = np.random.default_rng(3)
+    ai = rng.integers(0, t - 1, size=300)
+    pairs = sorted({(int(x), int(rng.integers(x + 1, t))) for x in ai})
+    Eref = oracle.random_edges(X, comps_ref, lam, seed, pairs=pairs)
+    got = _pair_sets(u, v, a, b)
+    ref = _pair_sets(Eref.u, Eref.v, Eref.a, Eref.b)
+    for key, val in ref.items():
+        assert got[key] == val, key
+    # refinement: a sample of edges followed through the rounds the GPU ran
+    pick = np.sort(rng.choice(len(u), size=3000, replace=False))
+    Es = _edges_to_oracle(u[pick], v[pick], w[pick], a[pick], b[pick])
+    Es.s = np.array([oracle.sqdist(oracle.as64(X), int(p), int(q)) for p, q in zip(Es.u, Es.v)])
+    rounds, deltas, conv = F.refine(Xd, G, E, max_rounds=10)
+    print("refine rounds", rounds, "deltas", deltas, flush=True)
+    for _ in range(rounds):
+        Es, _ = oracle.refine_edges(X, Gref, comp_ref, Es)
+    u2, v2, w2, _, _ = _edges_np(E)
+    assert np.array_equal(u2[pick], Es.u) and np.array_equal(v2[pick], Es.v)
+    np.testing.assert_allclose(w2[pick], np.sqrt(Es.s), rtol=1e-5)
+    # spanning tree over the kNN edges and the refined lambda-edges
+    tu, tv, tw, W = F.mst(Xd, nbr, dist, E)
+    tu, tv, tw = tu.cpu().numpy(), tv.cpu().numpy(), tw.cpu().numpy()
+    assert len(tu) == n - 1
+    ds = oracle.DisjointSet(n)
+    assert all(ds.union(int(p), int(q)) for p, q in zip(tu, tv))
+    assert abs(float(W[0]) - float(np.sum(tw.astype(np.float64)))) <= 1e-6 * float(W[0])

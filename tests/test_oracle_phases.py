@@ -206,3 +206,19 @@ def test_refine_equal_to_incumbent_not_taken(fn):
     E = oracle.EdgeSet(np.array([0]), np.array([2]), np.array([1.0]), np.array([0]), np.array([1]))
     R, delta = fn(X, G, comp, E)
     assert delta == 0 and int(R.u[0]) == 0
+
+
+def test_random_edges_pair_subset_equals_full_run():
+    X = datagen.blobs(n=500, d=5, n_clusters=6, seed=8)
+    nbr, _ = oracle.knn_exact(X, 1)
+    comp, comps = oracle.components(oracle.undirected_graph(nbr))
+    t = len(comps)
+    assert t >= 6
+    full = oracle.random_edges(X, comps, 3, seed=4)
+    sub = [(t - 2, t - 1), (0, 1), (1, t - 1), (0, t - 1)]
+    part = oracle.random_edges(X, comps, 3, seed=4, pairs=sub)
+    for a, b in sub:
+        m = (full.a == a) & (full.b == b)
+        p = (part.a == a) & (part.b == b)
+        assert np.array_equal(full.u[m], part.u[p]) and np.array_equal(full.v[m], part.v[p])
+        assert np.array_equal(full.s[m], part.s[p])
