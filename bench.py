@@ -44,7 +44,7 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 2860.3, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "3a63161b4bbd18bba18885c52e54fc712cf31f6e",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "6e7498088cd0865b510808ba7f8f877aeed8eeea",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 799.6, "write_GB": 0.407,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},

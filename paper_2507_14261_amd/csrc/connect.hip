@@ -144,13 +144,16 @@ __device__ __forceinline__ int64_t pair_start(int64_t a, int64_t t) {
 
 // One wave per component pair: lambda^2 samples drawn with Philox, their
 // float32 distances, and the lambda smallest by (s, sample).
+// CAP >= lambda^2 sample slots in LDS: 64 for lambda <= 8 (small enough for
+// many resident waves), 1024 up to lambda = 32.
+template <int CAP>
 __global__ __launch_bounds__(64) void lambda_edges_kernel(
     const float* __restrict__ X, int d, const CloudPairs* __restrict__ cp, int B, int lam,
     uint32_t key0, uint32_t key1, const int32_t* __restrict__ members,
     const int64_t* __restrict__ comp_ptr, int32_t* __restrict__ eu, int32_t* __restrict__ ev,
     float* __restrict__ ew, int32_t* __restrict__ ea, int32_t* __restrict__ eb) {
-  __shared__ SelectSmem<1024> sm;
-  __shared__ int su[1024], sv[1024];
+  __shared__ SelectSmem<CAP> sm;
+  __shared__ int su[CAP], sv[CAP];
   const int64_t p = blockIdx.x;
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
   // cloud of this pair
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(64) void lambda_edges_kernel(
     }
   }
   __syncthreads();
-  block_select<64, 1024>(sm, L, lam, tau32(d), d, [&](int i, const float** pa, const float** pb) {
+  block_select<64, CAP>(sm, L, lam, tau32(d), d, [&](int i, const float** pa, const float** pb) {
     *pa = X + (int64_t)su[i] * d;
     *pb = X + (int64_t)sv[i] * d;
   });
@@ -330,9 +333,10 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   }
   if (P > 0) {
     FAMST_HIP(hipMemcpyAsync(cp, hcp.data(), sizeof(CloudPairs) * B, hipMemcpyHostToDevice, s));
-    FAMST_TRY(launch("lambda_edges", lambda_edges_kernel, dim3((unsigned)P), dim3(64), 0, s, X, d,
-                     cp, B, lambda, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), members,
-                     comp_ptr, eu, ev, ew, ea, eb));
+    auto kern = lambda * lambda <= 64 ? lambda_edges_kernel<64> : lambda_edges_kernel<1024>;
+    FAMST_TRY(launch("lambda_edges", kern, dim3((unsigned)P), dim3(64), 0, s, X, d, cp, B, lambda,
+                     (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), members, comp_ptr, eu, ev,
+                     ew, ea, eb));
   }
   FAMST_HIP(hipStreamSynchronize(s));
   return FAMST_OK;

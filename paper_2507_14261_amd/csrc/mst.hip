@@ -80,27 +80,51 @@ __global__ void edge_compact_kernel(const uint64_t* __restrict__ keys, const uin
 // coprime to nchunk.  With many small clouds the host passes a large stride,
 // so that concurrent waves lower the minima of unrelated clouds rather than
 // the few components of one cloud; one cloud is taken in order (stride 1).
+// When every active lane of a wave lowers the same component (consecutive
+// lambda-edges of one component pair), the wave takes the minimum of its
+// keys first and issues one atomic.
 __global__ void bv_min_edge_kernel(const int32_t* __restrict__ elo, const int32_t* __restrict__ ehi,
                                    const uint32_t* __restrict__ ewb, const uint32_t* __restrict__ live,
                                    int64_t nlive, uint64_t stride, const int32_t* __restrict__ comp,
                                    unsigned long long* __restrict__ best, int64_t* __restrict__ keep) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nchunk = (nlive + 63) >> 6, w = t >> 6;
-  if (w >= nchunk) return;
+  if (w >= nchunk) return;   // uniform per wave
   const int64_t c =
       stride == 1 ? w : (int64_t)(((unsigned __int128)w * stride) % (unsigned __int128)nchunk);
   const int64_t i = (c << 6) + (t & 63);
-  if (i >= nlive) return;
-  const uint32_t e = live[i];
-  int cu = comp[elo[e]], cv = comp[ehi[e]];
-  if (cu == cv) {
-    keep[i] = 0;
-    return;
+  bool act = i < nlive;
+  int cu = -1, cv = -1;
+  unsigned long long key = ~0ull;
+  if (act) {
+    const uint32_t e = live[i];
+    cu = comp[elo[e]];
+    cv = comp[ehi[e]];
+    act = cu != cv;
+    keep[i] = act ? 1 : 0;
+    key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
   }
-  keep[i] = 1;
-  unsigned long long key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
-  if (key < __hip_atomic_load(&best[cu], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&best[cu], key);
-  if (key < __hip_atomic_load(&best[cv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&best[cv], key);
+  const unsigned long long am = ballot(act);
+  if (!am) return;   // uniform
+  const int lead = __builtin_ctzll(am);
+  auto lower = [&](int cc) {
+    const int c0 = __builtin_amdgcn_readlane(cc, lead);
+    if (ballot(act && cc != c0) == 0) {
+      // one component for the whole wave: minimum of the keys, one atomic
+      unsigned long long m = act ? key : ~0ull;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long om = __shfl_xor(m, o);
+        m = om < m ? om : m;
+      }
+      if ((t & 63) == lead && m < __hip_atomic_load(&best[c0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(&best[c0], m);
+    } else if (act && key < __hip_atomic_load(&best[cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      atomicMin(&best[cc], key);
+    }
+  };
+  lower(cu);
+  lower(cv);
 }
 
 __global__ void bv_compact_kernel(const uint32_t* __restrict__ live, const int64_t* __restrict__ keep,
