@@ -154,10 +154,11 @@ __global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X
                                                     float* __restrict__ ew,
                                                     const int32_t* __restrict__ ea,
                                                     const int32_t* __restrict__ eb, int64_t ne,
-                                                    unsigned long long* __restrict__ delta) {
+                                                    const int32_t* __restrict__ act_in,
+                                                    int64_t* __restrict__ changed_flag) {
   __shared__ RefineSmem sm;
-  const int64_t e = blockIdx.x;
-  if (e >= ne) return;
+  if ((int64_t)blockIdx.x >= ne) return;
+  const int64_t e = act_in ? act_in[blockIdx.x] : (int64_t)blockIdx.x;
   const int r16 = threadIdx.x & 15;
   const float tau = tau32(d);
   const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
@@ -183,11 +184,14 @@ __global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X
     vs = bv.id1;
     ds = bv.s1;
   }
-  if (threadIdx.x == 0 && (us != u || vs != v)) {
-    eu[e] = us;
-    ev[e] = vs;
-    ew[e] = __builtin_sqrtf(ds);
-    atomicAdd(delta, 1ull);
+  if (threadIdx.x == 0) {
+    const bool changed = us != u || vs != v;
+    if (changed) {
+      eu[e] = us;
+      ev[e] = vs;
+      ew[e] = __builtin_sqrtf(ds);
+    }
+    changed_flag[blockIdx.x] = changed ? 1 : 0;
   }
 }
 
@@ -208,10 +212,24 @@ __device__ Best row_argmin_group(const float* __restrict__ X, int d, const int64
   const int64_t p0 = row_ptr[row], p1 = row_ptr[row + 1];
   const float* xa = X + (int64_t)anchor * d;
   Best b{F_INF, 0x7FFFFFFF, F_INF};
-  for (int64_t p = p0; p < p1; ++p) {
-    const int x = col[p];
-    if (comp[x] != c || x == excl) continue;   // uniform within the group
-    best_push(b, sq32_group(X + (int64_t)x * d, xa, d, r16), x);
+  // sixteen neighbours at a time: lane r16 fetches neighbour p0 + r16 and
+  // its component, then the group measures the ones that qualify
+  const int gsh = threadIdx.x & 48;   // this group's first lane within the wave
+  for (int64_t q0 = p0; q0 < p1; q0 += 16) {
+    const int64_t p = q0 + r16;
+    int x = 0;
+    bool ok = false;
+    if (p < p1) {
+      x = col[p];
+      ok = comp[x] == c && x != excl;
+    }
+    unsigned m = (unsigned)(ballot(ok) >> gsh) & 0xFFFFu;
+    while (m) {
+      const int j = __builtin_ctz(m);
+      m &= m - 1;
+      const int xj = __shfl(x, j, 16);
+      best_push(b, sq32_group(X + (int64_t)xj * d, xa, d, r16), xj);
+    }
   }
   *used64 = false;
   const float up = 1.0f + 2.0f * tau, dn = 1.0f - 2.0f * tau;
@@ -246,11 +264,14 @@ __global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restri
                                                           float* __restrict__ ew,
                                                           const int32_t* __restrict__ ea,
                                                           const int32_t* __restrict__ eb, int64_t ne,
-                                                          unsigned long long* __restrict__ delta) {
-  const int r16 = threadIdx.x & 15, lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * RG_EDGES + (threadIdx.x >> 4);
+                                                          const int32_t* __restrict__ act_in,
+                                                          int64_t* __restrict__ changed_flag) {
+  const int r16 = threadIdx.x & 15;
+  const int64_t slot = (int64_t)blockIdx.x * RG_EDGES + (threadIdx.x >> 4);
+  int64_t e = 0;
   bool changed = false;
-  if (e < ne) {
+  if (slot < ne) {
+    e = act_in ? act_in[slot] : slot;
     const float tau = tau32(d);
     const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
     const float* xu = X + (int64_t)u * d;
@@ -274,14 +295,26 @@ __global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restri
       ds = bv.s1;
     }
     changed = us != u || vs != v;
-    if (changed && r16 == 0) {
-      eu[e] = us;
-      ev[e] = vs;
-      ew[e] = __builtin_sqrtf(ds);
+    if (r16 == 0) {
+      if (changed) {
+        eu[e] = us;
+        ev[e] = vs;
+        ew[e] = __builtin_sqrtf(ds);
+      }
+      changed_flag[slot] = changed ? 1 : 0;
     }
   }
-  const unsigned long long m = ballot(changed && r16 == 0);
-  if (lane == 0 && m) atomicAdd(delta, (unsigned long long)__popcll(m));
+}
+
+// The next round's edge list: the edges whose flag is set, at their
+// exclusive-scan positions (no shared counter: one per changed edge would
+// serialise on a single address).
+__global__ __launch_bounds__(256) void refine_compact_kernel(const int64_t* __restrict__ flag,
+                                                            const int64_t* __restrict__ pos,
+                                                            const int32_t* __restrict__ act_in, int64_t nact,
+                                                            int32_t* __restrict__ act_out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nact && flag[i]) act_out[pos[i]] = act_in ? act_in[i] : (int32_t)i;
 }
 
 }  // namespace famst
@@ -297,7 +330,14 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   if (n < 2 || d < 1 || n_edges < 0 || max_rounds < 1) return FAMST_EINVAL;
   if (n_edges >= (int64_t(1) << 31)) return FAMST_ENOTIMPL;
   Carve cv(ws);
-  unsigned long long* dc = cv.take<unsigned long long>(1);
+  // edges refined in a round: all in the first, then those the previous
+  // round changed (an unchanged edge stays unchanged: X, G and the labels
+  // are fixed); per-slot change flags, their exclusive scan, scan scratch
+  int32_t* act[2] = {cv.take<int32_t>(n_edges), cv.take<int32_t>(n_edges)};
+  int64_t* flag = cv.take<int64_t>(n_edges + 1);
+  int64_t* pos = cv.take<int64_t>(n_edges + 1);
+  const size_t tmpb = scan_i64_bytes((size_t)n_edges + 1);
+  void* tmp = cv.take<char>(tmpb);
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
@@ -307,20 +347,28 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
     return FAMST_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int r = 0;
-  unsigned long long last = 0;
+  int64_t last = 0;
+  int64_t nact = n_edges;
+  const int32_t* ain = nullptr;   // null: every edge
   while (r < max_rounds) {
-    FAMST_HIP(hipMemsetAsync(dc, 0, sizeof(unsigned long long), s));
-    if (n_edges >= FAMST_REFINE_GROUP_MIN)
-      FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(n_edges, RG_EDGES)), dim3(RNT), 0, s, X, d,
-                       row_ptr, col, comp, eu, ev, ew, ea, eb, n_edges, dc));
+    int32_t* aout = act[r & 1];
+    if (nact >= FAMST_REFINE_GROUP_MIN)
+      FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(nact, RG_EDGES)), dim3(RNT), 0, s, X, d,
+                       row_ptr, col, comp, eu, ev, ew, ea, eb, nact, ain, flag));
     else
-      FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr,
-                       col, comp, eu, ev, ew, ea, eb, n_edges, dc));
-    FAMST_HIP(hipMemcpyAsync(&last, dc, sizeof(last), hipMemcpyDeviceToHost, s));
+      FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)nact), dim3(RNT), 0, s, X, d, row_ptr, col,
+                       comp, eu, ev, ew, ea, eb, nact, ain, flag));
+    FAMST_HIP(hipMemsetAsync(flag + nact, 0, sizeof(int64_t), s));
+    FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, (size_t)nact + 1, s));
+    FAMST_TRY(launch("refine_compact", refine_compact_kernel, dim3(cdiv(nact, 256)), dim3(256), 0, s, flag,
+                     pos, ain, nact, aout));
+    FAMST_HIP(hipMemcpyAsync(&last, pos + nact, sizeof(last), hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipStreamSynchronize(s));
     if (deltas) deltas[r] = (int64_t)last;
     ++r;
     if (last == 0) break;
+    nact = last;
+    ain = aout;
   }
   *rounds_run = r;
   return last == 0 ? FAMST_OK : FAMST_WNOTCONVERGED;
