@@ -795,16 +795,18 @@ struct RerankArgs {
   const unsigned* gstat;
   float arith_c;          // screening arithmetic error factor (x 2^-24 folded in)
   const float* ubound;    // per-query bound of the rejected screened values (or null)
+  const int* order;       // block i re-ranks row order[i] (null: row i); the spatial order
+                          // of the screening, so that neighbouring blocks gather the same rows
   int* nbr;
   float* dist;
   float* kth_s;           // s of the k-th selected (for recomputation)
-  int* bad_rows;          // rows not certified
-  unsigned long long* counters;  // [0] not certified, [1] recomputed, [2] near ties
+  int64_t* bad_flag;      // per row: 1 if not certified (listed afterwards by a scan)
+  unsigned long long* counters;  // [1] recomputed, [2] near ties
 };
 
 __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
   __shared__ SelectSmem<64> sm;
-  const int64_t q = blockIdx.x;
+  const int64_t q = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int t = threadIdx.x;
   const int cb = find_cloud(a.offs, a.B, q);
   const int64_t nb = a.offs[cb + 1] - a.offs[cb];
@@ -867,11 +869,18 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
       float lb = rr > 0.f ? rr * rr * (1.0f - 1e-6f) : 0.f;
       cert = lb > kth * (1.0f + 2.0f * tau);
     }
-    if (!cert || invalid) {
-      unsigned long long p = atomicAdd(&a.counters[0], 1ull);
-      a.bad_rows[p] = (int)q;
-    }
+    a.bad_flag[q] = (!cert || invalid) ? 1 : 0;
   }
+}
+
+// The uncertified rows, in ascending order, at their exclusive-scan
+// positions (a shared counter would serialise on one address when most
+// rows are uncertified, as with float8 screening in approximate mode).
+__global__ __launch_bounds__(256) void list_flagged_kernel(const int64_t* __restrict__ flag,
+                                                          const int64_t* __restrict__ pos, int64_t n,
+                                                          int* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n && flag[i]) rows[pos[i]] = (int)i;
 }
 
 // Exact recomputation of a row: collect every point whose float32 distance
@@ -1169,6 +1178,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   float* kth = cv.take<float>(n);
   float* ub = cv.take<float>(n);
   int* bad = cv.take<int>(n);
+  int64_t* badf = cv.take<int64_t>(n + 1);
+  int64_t* badp = cv.take<int64_t>(n + 1);
+  const size_t btmpb = scan_i64_bytes((size_t)n + 1);
+  void* btmp = cv.take<char>(btmpb);
   unsigned long long* ctr = cv.take<unsigned long long>(4);
   int* ovf = cv.take<int>(1);
   // spatial order of the scan (one large cloud, pipelined or streamed
@@ -1272,13 +1285,22 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   ra.cand_j = cj; ra.cand_s = cs; ra.nq = nq; ra.qerr = qerr; ra.gstat = gstat;
   ra.arith_c = arith_c;
   ra.ubound = (p.piped || p.hd) ? ub : nullptr;
-  ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_rows = bad; ra.counters = ctr;
+  ra.order = spatial ? perm : nullptr;
+  ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_flag = badf; ra.counters = ctr;
   FAMST_TRY(launch("rerank", rerank_kernel, dim3((unsigned)n), dim3(64), 0, s, ra));
 
   unsigned long long hc[4] = {0, 0, 0, 0};
+  int64_t nbad = 0;
   if (exact || stats) {
+    FAMST_HIP(hipMemsetAsync(badf + n, 0, sizeof(int64_t), s));
+    FAMST_TRY(exclusive_scan_i64(btmp, btmpb, badf, badp, (size_t)n + 1, s));
+    if (exact)
+      FAMST_TRY(launch("list_flagged", list_flagged_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, badf, badp, n,
+                       bad));
+    FAMST_HIP(hipMemcpyAsync(&nbad, badp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipMemcpyAsync(hc, ctr, 32, hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipStreamSynchronize(s));
+    hc[0] = (unsigned long long)nbad;
   }
   if (exact && hc[0] > 0) {
     FAMST_TRY(launch("exact_row", exact_row_kernel, dim3((unsigned)hc[0]), dim3(256), 0, s, X, d,
@@ -1287,6 +1309,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
     FAMST_HIP(hipMemcpyAsync(hc, ctr, 32, hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipMemcpyAsync(&hov, ovf, 4, hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipStreamSynchronize(s));
+    hc[0] = (unsigned long long)nbad;
     if (hov) return FAMST_ECAPACITY;
   }
   if (stats) {
