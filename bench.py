@@ -43,6 +43,12 @@ MEASURED_TRAFFIC = {
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 2860.3, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
+    ("dist_topk", "vmf-4m-d96"): {
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "1b15179f0b0498188ba34125ab07a24a815caa2e",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
+        "fetch_GB": 11892.2, "write_GB": 1.152,
+        "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "6e7498088cd0865b510808ba7f8f877aeed8eeea",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
