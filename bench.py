@@ -38,7 +38,7 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 971.4, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "932dfef5ca9d812bbd4557204dd6ad45ccb674f5",
+        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "8a18d916fbc3df3c67f8555324527b19df567f00",
                     "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 2860.3, "write_GB": 0.130,

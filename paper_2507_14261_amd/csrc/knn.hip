@@ -945,6 +945,12 @@ struct KnnPlan {
   size_t lds;
 };
 
+// Zero rows past the end of the screening copy, its norms and scales: at
+// least the largest tile or query block a screening kernel reads whole.
+constexpr int PADR = 256;
+static_assert(HdShape<4>::BN <= PADR && HdShape<8>::BN <= PADR && hd_qblk<4>() <= PADR && hd_qblk<8>() <= PADR,
+              "padding covers every streamed tile and query block");
+
 static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
   p.prec = prec;
   p.KC = k_cand ? k_cand : (k <= 24 ? 32 : 64);
@@ -965,7 +971,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.hd = true;
     p.DP = (d + kdim - 1) / kdim * kdim;
     p.QB = 4;
-    p.qblk = 256;
+    p.qblk = prec == FAMST_FP32 ? hd_qblk<4>() : hd_qblk<8>();
     p.lds = prec == FAMST_FP32 ? hd_lds_bytes<4>() : hd_lds_bytes<8>();
   } else if (!p.chunked) {
     p.DP = p.nkb * kbw;
@@ -1050,17 +1056,17 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
                 ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);
 }
 
-template <int PREC, int NW>
+template <int PREC, int SH>
 static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                      const float* scl, const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
-  auto kern = dist_topk_hd_kernel<PREC, NW>;
+  auto kern = dist_topk_hd_kernel<PREC, SH>;
   static bool attr = false;
   if (!attr) {
     FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr = true;
   }
-  return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), hd_lds_bytes<NW>(), s, Xq, nq,
+  return launch("dist_topk", kern, dim3(nblk), dim3(64 * HdShape<SH>::NW), hd_lds_bytes<SH>(), s, Xq, nq,
                 p.DP * p.esz, desc, cj, cs, ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, scl,
                 ba.perm);
 }
@@ -1164,11 +1170,11 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   const int esz = p.esz;
 
   Carve cv(ws);
-  // the screening copy and its norms end with 256 zero rows (tile and query
-  // block reads of the pipelined kernels run up to 255 rows past a cloud)
-  void* Xq = cv.take<char>((size_t)(n + 256) * p.DP * esz);
-  float* nq = cv.take<float>(n + 256);
-  float* scl = cv.take<float>(n + 256);   // float8 row scales (+ padding, as the norms)
+  // the screening copy and its norms end with PADR zero rows (tile and query
+  // block reads of the screening kernels run up to PADR - 1 rows past a cloud)
+  void* Xq = cv.take<char>((size_t)(n + PADR) * p.DP * esz);
+  float* nq = cv.take<float>(n + PADR);
+  float* scl = cv.take<float>(n + PADR);   // float8 row scales (+ padding, as the norms)
   float* qerr = cv.take<float>(n);
   unsigned* gstat = cv.take<unsigned>(4);
   BlockDesc* desc = cv.take<BlockDesc>(nblk);
@@ -1193,9 +1199,9 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   uint16_t* skx = cv.take<uint16_t>(skn * 128);
   float* sknq = cv.take<float>(skn);
   const bool f8sp = skn && prec == FAMST_FP8_E4M3;   // permuted float8 row scales
-  float* sclp = cv.take<float>(f8sp ? skn + 256 : 0);
-  char* Xp = cv.take<char>((sn ? sn + 256 : 0) * p.DP * esz);
-  float* nqp = cv.take<float>(sn ? sn + 256 : 0);
+  float* sclp = cv.take<float>(f8sp ? skn + PADR : 0);
+  char* Xp = cv.take<char>((sn ? sn + PADR : 0) * p.DP * esz);
+  float* nqp = cv.take<float>(sn ? sn + PADR : 0);
   float* qerrp = cv.take<float>(sn);
   uint32_t* pkey = cv.take<uint32_t>(sn);
   uint32_t* pkey2 = cv.take<uint32_t>(sn);
@@ -1222,12 +1228,12 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e3 = hipMemsetAsync(gstat, 0, 16, s);
   hipError_t e4 = hipMemsetAsync(ctr, 0, 32, s);
   hipError_t e6 = hipMemsetAsync(ovf, 0, sizeof(int), s);
-  hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)256 * p.DP * esz, s);
-  hipError_t e8 = hipMemsetAsync(nq + n, 0, 256 * sizeof(float), s);
-  hipError_t e11 = hipMemsetAsync(scl + n, 0, 256 * sizeof(float), s);
-  hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)256 * p.DP * esz, s) : hipSuccess;
-  hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
-  hipError_t e12 = f8sp ? hipMemsetAsync(sclp + sn, 0, 256 * sizeof(float), s) : hipSuccess;
+  hipError_t e7 = hipMemsetAsync(static_cast<char*>(Xq) + (size_t)n * p.DP * esz, 0, (size_t)PADR * p.DP * esz, s);
+  hipError_t e8 = hipMemsetAsync(nq + n, 0, PADR * sizeof(float), s);
+  hipError_t e11 = hipMemsetAsync(scl + n, 0, PADR * sizeof(float), s);
+  hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)PADR * p.DP * esz, s) : hipSuccess;
+  hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, PADR * sizeof(float), s) : hipSuccess;
+  hipError_t e12 = f8sp ? hipMemsetAsync(sclp + sn, 0, PADR * sizeof(float), s) : hipSuccess;
   hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
   delete[] hd;
   if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11 || e12) return FAMST_EHIP;

@@ -19,42 +19,50 @@ namespace famst {
 // stage, 16-byte chunk c of staged row r sits at slot c ^ swz(r) of the row:
 // eight consecutive rows then cover all LDS banks, so the operand reads are
 // conflict-free.
-// Block shapes: NW waves of 16 QB queries (256 queries per block) against
-// tiles of BN rows in a ring of PIPE stages; each wave accumulates
-// QB x BN / 16 fragments (128 VGPRs).  bf16 takes the square 256 x 256
-// block (the streamed bytes per product are smallest: 36 % against 24 % of
-// the matrix-core peak at 960 dims) with one block per CU and four stages;
-// float32, four times slower per byte on the matrix cores, takes 256 x 128
-// with two blocks per CU and three stages.
-template <int NW> struct HdShape;
-template <> struct HdShape<4> { static constexpr int QB = 4, BN = 128, PIPE = 3, KSB = 64; };
-template <> struct HdShape<8> { static constexpr int QB = 2, BN = 256, PIPE = 2, KSB = 128; };
-template <int NW>
+// Block shapes (by id): NW waves of 16 QB queries (QBLK = 16 QB NW queries
+// per block) against tiles of BN rows, K-steps of KSB bytes in a ring of
+// PIPE stages; each wave accumulates QB x BN / 16 fragments (128 VGPRs).
+// SC: bytes per tile row beside its staged stretch (the norm, and with
+// float8 the row scale).
+//   4: float32, 4 waves, 256 x 128, 64-byte steps, three stages, two blocks
+//      per CU (four times slower per byte on the matrix cores);
+//   8: bf16 and float8, 8 waves, the square 256 x 256 block, 128-byte steps
+//      (two bf16 MFMA K-steps or one float8 K-step per barrier), two stages,
+//      one block per CU.
+template <int SH> struct HdShape;
+template <> struct HdShape<4> { static constexpr int NW = 4, QB = 4, BN = 128, PIPE = 3, KSB = 64, SC = 4; };
+template <> struct HdShape<8> { static constexpr int NW = 8, QB = 2, BN = 256, PIPE = 2, KSB = 128, SC = 8; };
+template <int SH>
+constexpr int hd_qblk() { return 16 * HdShape<SH>::QB * HdShape<SH>::NW; }
+template <int SH>
 constexpr size_t hd_stage_bytes() {
-  // query rows, tile rows, the tile's norms (and, in the 8-wave shape, the
-  // tile's float8 row scales)
-  return (size_t)256 * HdShape<NW>::KSB + (size_t)HdShape<NW>::BN * (HdShape<NW>::KSB + (NW == 8 ? 8 : 4));
+  // query rows, tile rows, the tile's norms (and row scales)
+  return (size_t)hd_qblk<SH>() * HdShape<SH>::KSB + (size_t)HdShape<SH>::BN * (HdShape<SH>::KSB + HdShape<SH>::SC);
 }
-template <int NW>
-constexpr size_t hd_lds_bytes() { return (size_t)HdShape<NW>::PIPE * hd_stage_bytes<NW>(); }
+template <int SH>
+constexpr size_t hd_lds_bytes() { return (size_t)HdShape<SH>::PIPE * hd_stage_bytes<SH>(); }
 
-template <int PREC, int NW>
-__global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
+template <int PREC, int SH>
+__global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dist_topk_hd_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int RS,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
     float tau, float* __restrict__ ubound, const float* __restrict__ scl, const int* __restrict__ perm) {
-  constexpr int QB = HdShape<NW>::QB, BN = HdShape<NW>::BN, KC = 32, QW = 16 * QB, JB = BN / 16;
+  constexpr int NW = HdShape<SH>::NW, QB = HdShape<SH>::QB, BN = HdShape<SH>::BN, KC = 32, QW = 16 * QB,
+                JB = BN / 16, QBLK = hd_qblk<SH>();
   constexpr bool F8 = PREC == FAMST_FP8_E4M3;   // per-row scales: s = |y|^2 - 2 a_x a_y codes.codes
-  static_assert(!F8 || (NW == 8 && HdShape<NW>::KSB == 128), "float8: one 128-dim K-step per stage");
-  constexpr int HD_PIPE = HdShape<NW>::PIPE, KSB = HdShape<NW>::KSB;
+  static_assert(!F8 || (HdShape<SH>::KSB == 128 && HdShape<SH>::SC == 8 && BN / 64 < NW),
+                "float8: one 128-dim K-step per stage, scales staged by the second half of the waves");
+  static_assert(BN / 64 <= NW && (NW & (BN / 64 - 1)) == 0, "norm loads: one wave per 64 tile rows");
+  constexpr int HD_PIPE = HdShape<SH>::PIPE, KSB = HdShape<SH>::KSB;
   constexpr int CPR = KSB / 16, KX = KSB / 64;   // 16-byte chunks per staged row; MFMA K-steps per stage
   // chunk c of staged row r sits at slot c ^ swz(r): eight consecutive rows
   // then cover all 32 banks for 64-byte and for 128-byte rows
   auto swz = [](int r) { return CPR == 4 ? ((r >> 1) & 3) : (r & 7); };
   constexpr int NT = 64 * NW;
-  constexpr int SQ = 256 * KSB, SR = BN * KSB, STG = (int)hd_stage_bytes<NW>();
-  constexpr int NLQ = 256 * CPR / NT, NLR = BN * CPR / NT;   // 16-byte query / row chunks per thread
+  constexpr int SQ = QBLK * KSB, SR = BN * KSB, STG = (int)hd_stage_bytes<SH>();
+  constexpr int NLQ = QBLK * CPR / NT, NLR = BN * CPR / NT;   // 16-byte query / row chunks per thread
+  static_assert(NLQ * NT == QBLK * CPR && NLR * NT == BN * CPR, "whole chunks per thread");
   constexpr int NLD = NLQ + NLR + 1;                  // loads per thread per stage (+ one norm)
   using LS = typename ListRegs<QW>::S;
   using LJ = typename ListRegs<QW>::J;
@@ -92,7 +100,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_hd_kernel(
   }
 
   // this thread's source offsets within the staged query block and row tile
-  // (the copy holds 256 padding rows past its end: no clamps)
+  // (the copy holds PADR >= BN padding rows past its end: no clamps)
   unsigned qoff[NLQ], roff[NLR];
 #pragma unroll
   for (int i = 0; i < NLQ; ++i) {
