@@ -41,14 +41,20 @@ __global__ void unique_flags_kernel(const uint64_t* __restrict__ keys, int64_t m
   flag[p] = keep ? 1 : 0;
 }
 
+// Columns at their scan positions.  The keys are sorted by (row, column),
+// so row u starts at the scan position of its first key (kept or not): the
+// number of kept keys in the rows before it.  Every row has keys (its own k
+// neighbours), and the end is the total.
 __global__ void csr_fill_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ flag,
-                                const int64_t* __restrict__ pos, int64_t m,
-                                int32_t* __restrict__ col, int64_t* __restrict__ rowcnt) {
+                                const int64_t* __restrict__ pos, int64_t m, int64_t n,
+                                int32_t* __restrict__ col, int64_t* __restrict__ row_ptr) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= m || !flag[p]) return;
-  uint64_t kk = keys[p];
-  col[pos[p]] = (int32_t)(uint32_t)kk;
-  atomicAdd(reinterpret_cast<unsigned long long*>(&rowcnt[kk >> 32]), 1ull);
+  if (p >= m) return;
+  const uint64_t kk = keys[p];
+  const uint32_t u = (uint32_t)(kk >> 32);
+  if (p == 0 || (uint32_t)(keys[p - 1] >> 32) != u) row_ptr[u] = pos[p];
+  if (p == m - 1) row_ptr[n] = pos[m];
+  if (flag[p]) col[pos[p]] = (int32_t)(uint32_t)kk;
 }
 
 // ------------------------------------------------------ components
@@ -239,7 +245,6 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   uint64_t* skeys = cv.take<uint64_t>(m);
   int64_t* flag = cv.take<int64_t>(m + 1);
   int64_t* pos = cv.take<int64_t>(m + 1);
-  int64_t* rowcnt = cv.take<int64_t>(n + 1);
   int* parent = cv.take<int>(n);
   int64_t* isroot = cv.take<int64_t>(n + 1);
   int64_t* lab = cv.take<int64_t>(n + 1);
@@ -274,10 +279,8 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
                    m, flag));
   FAMST_HIP(hipMemsetAsync(flag + m, 0, sizeof(int64_t), s));
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, m + 1, s));
-  FAMST_TRY(fill_i64(rowcnt, 0, n + 1, s));
   FAMST_TRY(launch("graph_fill", csr_fill_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, skeys, flag,
-                   pos, m, col, rowcnt));
-  FAMST_TRY(exclusive_scan_i64(tmp, tmpb, rowcnt, row_ptr, n + 1, s));
+                   pos, m, n, col, row_ptr));
   // ---- components
   FAMST_TRY(iota_i32(parent, n, s));
   uint64_t stride = 1;   // one cloud: in order; several: odd, coprime to n k (checked)
