@@ -327,6 +327,7 @@ def main():
     rows = np.sort(rng.choice(n, size=args.cpu_rows, replace=False))
     cpu = None
     parity = None
+    oracle_w = None
     if not args.no_cpu_baseline:
         ref_nbr, t_cpu = cpu_baseline(X, k, rows)
         nb_b = out_b.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
@@ -337,6 +338,20 @@ def main():
         if out_8 is not None:
             nb_8 = out_8.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
             parity["recall_fp8"] = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_8, ref_nbr)]))
+        if args.workload == "blobs-10k-d32":
+            # weight error against the oracle's FAMST and against the exact MST
+            # (float64 Prim on the complete graph): seconds on the host here
+            import oracle
+            t0 = time.perf_counter()
+            ref = oracle.famst(X, k, lam, seed=args.seed, max_rounds=args.rounds)
+            exact_w = oracle.prim_exact(X)[3]
+            log(f"oracle FAMST and exact MST: {time.perf_counter() - t0:.1f} s")
+            oracle_w = {"W_oracle_famst": ref.W, "W_exact_mst": exact_w,
+                        "rel_err_bf16_vs_oracle": abs(Wb - ref.W) / ref.W,
+                        "rel_err_fp32_vs_oracle": abs(Wf - ref.W) / ref.W,
+                        "famst_rel_err_vs_exact_mst": (Wf - exact_w) / exact_w}
+            if out_8 is not None:
+                oracle_w["rel_err_fp8_vs_oracle"] = abs(W8 - ref.W) / ref.W
         cores = len(os.sched_getaffinity(0))
         cpu = {"value": round(len(rows) / t_cpu, 3), "unit": "points/s", "cores": cores, "kind": "oracle",
                "sample": (f"exact float64 kNN (the oracle's Phase 1, the dominant phase) of {len(rows)} "
@@ -370,7 +385,8 @@ def main():
         "measured_peaks": pk,
         "cpu_baseline": cpu,
         "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf,
-                   "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None},
+                   "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None,
+                   **(oracle_w or {})},
         "fp32_path": None if args.skip_fp32 else {
                       "ms_per_step": round(ms_fp32, 3), "points_per_s": round(n / (ms_fp32 * 1e-3), 1),
                       "dist_topk_avg_ms": round(avg_f, 3),
