@@ -145,6 +145,7 @@ def bench_clouds(args, F, torch):
         return out, g
 
     res = {}
+    last = {}
     for name, fn, kern in [("exact", exact_step, "dense_prim_fused"), ("k16", knn_step, "dist_topk")]:
         for _ in range(args.warmup):
             fn()
@@ -157,6 +158,7 @@ def bench_clouds(args, F, torch):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         F.profile_enable(False)
+        last[name] = out
         nl, ms = F.profile_read(kern)
         res[name] = {"ms_per_step": (t1 - t0) * 1e3 / args.steps, "kernel": kern,
                      "kernel_avg_ms": ms / nl if nl else None, "phases": {}}
@@ -168,6 +170,10 @@ def bench_clouds(args, F, torch):
     # one launch reads sum_i n_i (n_i - 1) / 2 rows of d float32 values
     sizes = np.diff(offs).astype(np.float64)
     prim_bytes = float(np.sum(sizes * (sizes - 1) / 2)) * d * 4
+    # weight error of the k = 16 FAMST trees against the exact trees, per cloud
+    W_exact = last["exact"][3].double().cpu().numpy()
+    W_k16 = last["k16"][0].W.double().cpu().numpy()
+    rel = (W_k16 - W_exact) / W_exact
     ex = res["exact"]
     val = n / (ex["ms_per_step"] * 1e-3)
     gbs = prim_bytes / (ex["kernel_avg_ms"] * 1e-3) / 1e9 if ex["kernel_avg_ms"] else None
@@ -185,6 +191,8 @@ def bench_clouds(args, F, torch):
                      "avg_ms": round(ex["kernel_avg_ms"], 3) if ex["kernel_avg_ms"] else None,
                      "algorithmic_GB": round(prim_bytes / 1e9, 3)},
         "k16_path": {"ms_per_step": round(res["k16"]["ms_per_step"], 3),
+                     "weight_rel_err_vs_exact_mst": {"max": float(rel.max()), "mean": float(rel.mean()),
+                                                     "min": float(rel.min()), "clouds": int(len(rel))},
                      "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1),
                      "phases_ms_per_step": res["k16"]["phases"]},
         "cpu_baseline": None,
