@@ -279,6 +279,19 @@ def main():
     log(f"generated {args.workload}: n={n} d={d} in {time.perf_counter() - t0:.1f}s")
     Xd = torch.from_numpy(X).to("cuda:0")
     torch.cuda.synchronize()
+    # host -> device upload of X, outside every timed region (the library
+    # takes device pointers; value is the rate on resident input): the best
+    # of three uploads from pinned host memory
+    Xh = torch.from_numpy(X).pin_memory()
+    h2d = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xd.copy_(Xh, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d.append(time.perf_counter() - t0)
+    h2d_s = min(h2d)
+    del Xh
 
     ms_bf16, out_b, phases_b = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, "bf16", False,
                                          args.steps, args.warmup, True)
@@ -392,6 +405,8 @@ def main():
                      "frac_of_measured": round(achieved / pk["mfma_bf16_tflops"], 4) if pk and achieved else None},
         "measured_peaks": pk,
         "cpu_baseline": cpu,
+        "h2d": {"bytes": int(X.nbytes), "ms": round(h2d_s * 1e3, 3), "GB_per_s": round(X.nbytes / h2d_s / 1e9, 1),
+                "points_per_s_with_upload": round(n / (ms_bf16 * 1e-3 + h2d_s), 1)},
         "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf,
                    "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None,
                    **(oracle_w or {})},
