@@ -351,6 +351,12 @@ def main():
     oracle_w = None
     if not args.no_cpu_baseline:
         ref_nbr, t_cpu = cpu_baseline(X, k, rows)
+        # the same oracle on one thread (BLAS limited to one), on the first
+        # twelfth of the sampled rows
+        from threadpoolctl import threadpool_limits
+        rows1 = rows[:max(64, len(rows) // 12)]
+        with threadpool_limits(limits=1):
+            _, t_cpu1 = cpu_baseline(X, k, rows1)
         nb_b = out_b.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
         nb_f = out_f.nbr[torch.from_numpy(rows).to(Xd.device)].cpu().numpy()
         rec_b = float(np.mean([len(set(a) & set(b)) / k for a, b in zip(nb_b, ref_nbr)]))
@@ -376,7 +382,9 @@ def main():
         cores = len(os.sched_getaffinity(0))
         cpu = {"value": round(len(rows) / t_cpu, 3), "unit": "points/s", "cores": cores, "kind": "oracle",
                "sample": (f"exact float64 kNN (the oracle's Phase 1, the dominant phase) of {len(rows)} "
-                          f"query rows against all {n} points; {t_cpu:.1f} s")}
+                          f"query rows against all {n} points; {t_cpu:.1f} s"),
+               "single_thread": {"value": round(len(rows1) / t_cpu1, 3), "cores": 1,
+                                 "sample": f"the first {len(rows1)} of those rows; {t_cpu1:.1f} s"}}
 
     res = {
         "metric": "points/s to approx MST at stated weight error, BF16/FP8+rerank vs FP32",
