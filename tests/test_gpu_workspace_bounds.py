@@ -57,6 +57,16 @@ def test_knn_graph_stays_in_workspace(guarded, n, d, prec):
     _check(guarded)
 
 
+def test_many_component_pipeline_stays_in_workspace(guarded):
+    # k = 1: hundreds of components, over 32768 lambda-edges (group-per-edge
+    # refinement with change flags and compaction, 64-slot lambda sampling)
+    X = torch.from_numpy(datagen.blobs(n=3000, d=32, n_clusters=10, seed=9)).to(DEV)
+    out = F.famst(X, 1, 5, seed=0, precision="fp32")
+    print("components", out.graph.n_comp, "edges", len(out.E), flush=True)
+    assert len(out.E) >= 32768
+    _check(guarded)
+
+
 def test_pipeline_entry_points_stay_in_workspace(guarded):
     X = torch.from_numpy(datagen.blobs(n=3000, d=32, n_clusters=10, seed=5)).to(DEV)
     F.famst(X, 10, 5, seed=0, precision="bf16")
