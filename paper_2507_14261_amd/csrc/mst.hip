@@ -362,11 +362,14 @@ __device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
 // flight.  CMAX >= nb / PRIM_NT.
 constexpr int PRIM_COMPACT = 32;
 
+#ifndef FAMST_PRIM_R
+#define FAMST_PRIM_R 8
+#endif
 template <bool VEC, int CMAX, class Emit>
 __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int nb,
                            uint64_t* __restrict__ keys, uint64_t* __restrict__ wkeys,
                            int* __restrict__ mcount, Emit emit) {
-  constexpr int NW = PRIM_NT / 64, NQ = PRIM_NT / 4, R = 4;
+  constexpr int NW = PRIM_NT / 64, NQ = PRIM_NT / 4, R = FAMST_PRIM_R;   // rows in flight per lane
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, c = t & 3, g = t >> 2;
   // vertex 0 starts the tree; every other vertex has the placeholder edge
   // (+inf, 0, j), replaced in the first step
