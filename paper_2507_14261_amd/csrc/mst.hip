@@ -358,8 +358,8 @@ __device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
 // by its owner; every PRIM_COMPACT steps the live entries are packed to the
 // front (their order does not matter: the minimum is over unique keys).
 // emit(step, p, j, w) is called by thread 0 for each edge, in insertion
-// order.  VEC: d == 64 and rows 16-byte aligned; four rows per quad are in
-// flight.  CMAX >= nb / PRIM_NT.
+// order.  VEC: d == 64 and rows 16-byte aligned; FAMST_PRIM_R rows per
+// quad are in flight.  CMAX >= nb / PRIM_NT.
 constexpr int PRIM_COMPACT = 32;
 
 #ifndef FAMST_PRIM_R
