@@ -50,7 +50,7 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 11892.2, "write_GB": 1.152,
         "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "b5b7c1f397842a3379d784f23bc44ee04ddbdc87",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "5a7f4347b68eaf06acc8836f66e8896534e37b7c",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
         "fetch_GB": 805.6, "write_GB": 0.409,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},

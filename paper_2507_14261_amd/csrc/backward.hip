@@ -104,7 +104,8 @@ extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const in
   FAMST_TRY(fill_i64(deg, 0, n + 1, s));
   FAMST_TRY(launch("incid_keys", incid_keys_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, tu, tv, m, n,
                    keys, deg, bad));
-  FAMST_TRY(sort_keys_u64(tmp, tmpb, keys, skeys, 2 * m, 64, s));
+  // (vertex << 32 | edge) keys: the vertex needs bits_for(n) bits
+  FAMST_TRY(sort_keys_u64(tmp, tmpb, keys, skeys, 2 * m, 32 + bits_for(n), s));
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, deg, ptr, n + 1, s));
   int hbad = 0;
   FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -734,7 +734,9 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   FAMST_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
   FAMST_TRY(launch("mst_keys", mst_keys_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, nbr, dist, n, k,
                    eu, ev, ew, n_edges, offs_d, B, keys, vals, bad));
-  FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, keys, skeys, vals, svals, m0, 64, s));
+  // (min << 32 | max) keys need 32 + bits_for(n) bits; KEY_NONE is all ones
+  // there too, so it still sorts after every edge
+  FAMST_TRY(sort_pairs_u64_u32(tmp, tmpb, keys, skeys, vals, svals, m0, 32 + bits_for(n), s));
   FAMST_TRY(launch("edge_unique", edge_unique_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, skeys, m0,
                    flag));
   FAMST_HIP(hipMemsetAsync(flag + m0, 0, sizeof(int64_t), s));
