@@ -76,17 +76,23 @@ __device__ __forceinline__ int uf_find(int* parent, int x) {
   }
 }
 
-// Thread t takes edge (t * stride) mod (n k), a bijection for a stride
-// coprime to n k.  With many small clouds the host passes a large stride:
-// concurrent threads then work on unrelated clouds rather than on one
-// cloud whose edges soon share a root (atomics on one address serialise).
-// One cloud is taken in order (stride 1: coalesced reads).
+// The edges are taken in chunks of 64 (one wave, coalesced reads): wave w
+// takes chunk (w * stride) mod nchunk, a bijection for a stride coprime to
+// nchunk.  Concurrent waves then hook unrelated parts of the graph rather
+// than neighbouring vertices whose edges soon share a root (its atomics
+// serialise): with many small clouds, and with one cloud whose points are
+// grouped by cluster.  The partition does not depend on the order.
+#ifndef FAMST_UF_STRIDE
+#define FAMST_UF_STRIDE 1009
+#endif
 __global__ void uf_hook_kernel(const int32_t* __restrict__ nbr, int64_t n, int k, uint64_t stride,
                                int* __restrict__ parent) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * k) return;
-  const int64_t e =
-      stride == 1 ? t : (int64_t)(((unsigned __int128)t * stride) % (unsigned __int128)(n * k));
+  const int64_t nk = n * k, nchunk = (nk + 63) >> 6, w = t >> 6;
+  if (w >= nchunk) return;
+  const int64_t c = stride == 1 ? w : (int64_t)(((unsigned __int128)w * stride) % (unsigned __int128)nchunk);
+  const int64_t e = (c << 6) + (t & 63);
+  if (e >= nk) return;
   int a = (int)(e / k), b = nbr[e];
   if (b < 0 || b >= n) return;
   while (true) {
@@ -283,13 +289,13 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
                    pos, m, n, col, row_ptr));
   // ---- components
   FAMST_TRY(iota_i32(parent, n, s));
-  uint64_t stride = 1;   // one cloud: in order; several: odd, coprime to n k (checked)
-  if (B > 1) {
-    stride = 1000003;
-    while (std::gcd(stride, (uint64_t)(n * k)) != 1) stride += 2;
-  }
-  FAMST_TRY(launch("uf_hook", uf_hook_kernel, dim3(cdiv(n * k, 256)), dim3(256), 0, s, nbr, n, k,
-                   stride % (uint64_t)(n * k), parent));
+  // chunk order for the hooks: a stride coprime to the chunk count (checked)
+  const uint64_t nchunk = (uint64_t)((n * k + 63) >> 6);
+  uint64_t stride = nchunk > 1 ? FAMST_UF_STRIDE : 1;
+  if (stride > 1)
+    while (std::gcd(stride, nchunk) != 1) ++stride;
+  FAMST_TRY(launch("uf_hook", uf_hook_kernel, dim3(cdiv((int64_t)nchunk * 64, 256)), dim3(256), 0, s, nbr, n,
+                   k, stride % nchunk, parent));
   FAMST_TRY(launch("uf_roots", uf_roots_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, s, parent, n,
                    isroot));
   FAMST_TRY(exclusive_scan_i64(tmp, tmpb, isroot, lab, n + 1, s));
