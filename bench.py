@@ -217,6 +217,39 @@ def cpu_baseline(X, k, rows):
     return nbr, t1 - t0
 
 
+def bench_sweep(args, F, torch):
+    """Parameter sweeps on synthetic blobs (one JSON line).
+    kl: k in {5, 10, 15, 20} x lambda in {1, 2, 3, 4, 5, 10} on 10,000 x 32
+        points: relative weight error against the exact tree (dense Prim on
+        the complete graph), components t, refinement rounds, time per step.
+    n:  n in {32k, 64k, 128k, 256k, 512k, 1024k} x 32 at k = 10, lambda = 5:
+        time per step and the per-phase breakdown."""
+    import datagen
+    rows = []
+    if args.sweep == "kl":
+        X = torch.from_numpy(datagen.blobs(n=10_000, d=32, seed=0)).to("cuda:0")
+        W_exact = float(F.mst(X, algo="prim")[3][0].item())
+        for k in (5, 10, 15, 20):
+            for lam in (1, 2, 3, 4, 5, 10):
+                ms, out, _ = time_path(F, torch, X, k, lam, args.seed, args.rounds, "fp32", True, 3, 1, False)
+                W = float(out.W[0].item())
+                rows.append({"k": k, "lambda": lam, "t": out.graph.n_comp[0], "rounds": out.rounds,
+                             "ms_per_step": round(ms, 3), "W": W, "rel_err_vs_exact": (W - W_exact) / W_exact})
+                log(f"k={k} lambda={lam}: {rows[-1]}")
+        config = {"workload": "blobs-10k-d32", "precision": "fp32 screening, exact", "W_exact_mst": W_exact}
+    else:
+        for n in (32_768, 65_536, 131_072, 262_144, 524_288, 1_048_576):
+            X = torch.from_numpy(datagen.blobs(n=n, d=32, seed=0)).to("cuda:0")
+            ms, out, ph = time_path(F, torch, X, 10, 5, args.seed, args.rounds, "bf16", False, 3, 1, True)
+            rows.append({"n": n, "ms_per_step": round(ms, 3), "points_per_s": round(n / (ms * 1e-3), 1),
+                         "t": out.graph.n_comp[0], "rounds": out.rounds,
+                         "phases_ms_per_step": {kk: round(v["total_ms"] / 3, 3) for kk, v in ph.items()}})
+            log(f"n={n}: {rows[-1]['ms_per_step']} ms")
+        config = {"workload": "blobs-d32", "k": 10, "lambda": 5, "precision": "bf16 screening + fp32 re-rank"}
+    return {"metric": f"parameter sweep ({args.sweep})", "unit": "see rows", "n_gpus": 1,
+            "data": "synthetic", "config": config, "rows": rows}
+
+
 def measure_peaks():
     """Measured ceilings of this device (outside every timed region): dense
     MFMA throughput of the three forms the screening issues (every wave of a
@@ -247,6 +280,8 @@ def main():
     ap.add_argument("--skip-fp32", action="store_true", help="do not time the float32-screened path")
     ap.add_argument("--skip-fp8", action="store_true", help="do not time the float8-screened path")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured MFMA / HBM ceilings")
+    ap.add_argument("--sweep", choices=["kl", "n"], default=None,
+                    help="parameter sweep on blobs instead of the timed workload (one JSON line)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a plain device copy of X (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -260,6 +295,9 @@ def main():
     import paper_2507_14261_amd as F
 
     F.load()
+    if args.sweep:
+        print(json.dumps(bench_sweep(args, F, torch)), flush=True)
+        return
     if args.workload == "clouds-256-d64":
         res = bench_clouds(args, F, torch)
         pk = None if args.no_peaks else measure_peaks()
