@@ -207,3 +207,27 @@ def test_recall():
     a = np.array([[1, 2], [0, 2]])
     b = np.array([[2, 1], [0, 3]])
     assert oracle.recall_at_k(a, b) == 0.75
+
+
+def test_famst_degenerate_inputs_closed_forms():
+    # two points: the tree is the one edge
+    X2 = np.array([[0.5, -1.0, 2.0], [1.5, 1.0, 0.0]])
+    r = oracle.famst(X2, 1, 3)
+    assert math.isclose(r.W, 3.0, rel_tol=1e-15) and len(r.tu) == 1
+    # three points, k = 1: the 1-NN graph of a triangle is its MST, whose
+    # weight is the perimeter minus the longest side
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        X3 = rng.standard_normal((3, 2))
+        dd = [np.linalg.norm(X3[a] - X3[b]) for a, b in ((0, 1), (0, 2), (1, 2))]
+        assert math.isclose(oracle.famst(X3, 1, 2).W, sum(dd) - max(dd), rel_tol=1e-12)
+    # points on a line: the exact tree joins neighbours in sorted order, so
+    # its weight is max - min; FAMST's tree weighs no less
+    x = np.random.default_rng(6).standard_normal((400, 1))
+    span = float(x.max() - x.min())
+    assert math.isclose(oracle.prim_exact(x)[3], span, rel_tol=1e-12)
+    r = oracle.famst(x, 2, 4, seed=1)
+    assert r.W >= span * (1 - 1e-12) and r.spanning and len(r.tu) == 399
+    # identical points: every distance is zero
+    r = oracle.famst(np.ones((50, 4)), 3, 2)
+    assert r.W == 0.0 and len(r.tu) == 49 and r.spanning
