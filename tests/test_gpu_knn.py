@@ -106,7 +106,8 @@ def test_knn_deterministic():
 @pytest.mark.parametrize("prec,d", [("fp32", 200), ("bf16", 300), ("fp8", 64), ("fp8", 130), ("bf16", 960)])
 def test_knn_chunked_and_fp8_exact_mode_matches_oracle(prec, d):
     # d beyond the register-resident kernel, and float8 at any d, use the
-    # K-chunked kernel; exact mode must still give the exact neighbour sets
+    # streamed-operand kernel at k' = 32; exact mode must still give the
+    # exact neighbour sets
     print(f"case prec={prec} d={d}", flush=True)
     X = datagen.blobs(n=1500, d=d, n_clusters=6, seed=d)
     nbr, dist, st = _run(X, 12, precision=prec, exact=True)
@@ -207,3 +208,28 @@ def test_knn_streamed_spatial_order_sampled_rows(prec, d):
     # every row's list holds k distinct other points
     srt = np.sort(nbr, axis=1)
     assert np.all(np.diff(srt, axis=1) > 0) and np.all(nbr != np.arange(n)[:, None])
+
+
+# k above 24 takes candidate lists of k' = 64: the LDS-list kernel up to 256
+# dimensions (bf16) or 128 (fp32), also with fewer K-blocks than its
+# template holds (d = 200 bf16, d = 100 fp32: 7 of 8), the K-chunked kernel
+# beyond that and for float8; k = 64 is the largest k the entry point takes
+@pytest.mark.parametrize("n,d,k,prec", [(1000, 32, 64, "fp32"), (777, 128, 64, "bf16"), (700, 200, 30, "bf16"),
+                                        (400, 100, 48, "fp32"), (700, 300, 40, "bf16"), (513, 200, 64, "fp32"),
+                                        (600, 64, 25, "fp8"), (900, 130, 64, "fp8")])
+def test_knn_large_k_lists_match_oracle(n, d, k, prec):
+    print(f"case n={n} d={d} k={k} {prec}", flush=True)
+    X = datagen.blobs(n=n, d=d, n_clusters=5, seed=3 * n + d)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True)
+    print("stats", st, flush=True)
+    _check_exact(X, k, nbr, dist)
+
+
+def test_famst_k64_end_to_end():
+    X = datagen.blobs(n=1500, d=16, n_clusters=8, seed=21)
+    print("case famst n=1500 d=16 k=64 lam=3", flush=True)
+    ref = oracle.famst(X, 64, 3, seed=5)
+    out = F.famst(torch.from_numpy(X).to(DEV), 64, 3, seed=5, precision="fp32")
+    W = float(out.W[0].item())
+    assert abs(W - ref.W) <= 1e-5 * ref.W
+    assert out.deltas == ref.deltas and len(out.tu) == len(X) - 1
