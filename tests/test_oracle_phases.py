@@ -222,3 +222,53 @@ def test_random_edges_pair_subset_equals_full_run():
         p = (part.a == a) & (part.b == b)
         assert np.array_equal(full.u[m], part.u[p]) and np.array_equal(full.v[m], part.v[p])
         assert np.array_equal(full.s[m], part.s[p])
+
+
+def _first_draws(comps, lam, seed, cloud=0):
+    # with every point at the same place all samples tie, and the stable
+    # selection keeps the first lambda draws of each pair in sample order
+    n = 1 + max(int(max(c)) for c in comps)
+    E = oracle.random_edges(np.zeros((n, 2)), comps, lam, seed, cloud)
+    return E.u.reshape(-1, lam), E.v.reshape(-1, lam)
+
+
+def test_random_edges_draws_uniform_and_independent():
+    # Alg. 3 draws u uniformly from C_a and v uniformly from C_b, each sample
+    # independently: the joint counts over C_a x C_b are flat, also for
+    # component sizes that are not powers of two and members in any order
+    from scipy.stats import chisquare
+    Ca, Cb = np.array([7, 2, 9]), np.array([0, 4, 5, 11, 3])
+    lam = 8
+    joint = np.zeros((3, 5))
+    same_all = 0
+    for seed in range(1000):
+        u, v = _first_draws([Ca, Cb], lam, seed)
+        assert set(u[0].tolist()) <= set(Ca.tolist()) and set(v[0].tolist()) <= set(Cb.tolist())
+        for a, b in zip(u[0], v[0]):
+            joint[list(Ca).index(a), list(Cb).index(b)] += 1
+        same_all += len(set(zip(u[0].tolist(), v[0].tolist()))) == 1
+    assert chisquare(joint.ravel()).pvalue > 1e-3
+    assert same_all <= 2
+    # equal sizes: u's and v's positions agree a quarter of the time (they
+    # would always agree if both came from one generator word)
+    C4a, C4b = np.array([0, 1, 2, 3]), np.array([4, 5, 6, 7])
+    agree, tot = 0, 0
+    for seed in range(400):
+        u, v = _first_draws([C4a, C4b], lam, seed)
+        agree += int(np.sum(u[0] == v[0] - 4))
+        tot += lam
+    assert abs(agree / tot - 0.25) < 0.03
+
+
+def test_random_edges_counters_separate_pairs_and_clouds():
+    # every (pair, sample, cloud) has its own counter: other pairs and other
+    # clouds see other draws
+    comps = [np.arange(0, 50), np.arange(50, 100), np.arange(100, 150)]
+    u0, v0 = _first_draws(comps, 6, seed=9, cloud=0)
+    u1, v1 = _first_draws(comps, 6, seed=9, cloud=1)
+    assert not np.array_equal(u0, u1) and not np.array_equal(v0, v1)
+    # pairs (0,1) and (0,2) share C_0: their u draws differ
+    assert not np.array_equal(u0[0], u0[1])
+    # the same run twice is the same
+    u2, v2 = _first_draws(comps, 6, seed=9, cloud=0)
+    assert np.array_equal(u0, u2) and np.array_equal(v0, v2)
