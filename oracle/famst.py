@@ -38,9 +38,11 @@ design notes of the repository):
   * Kruskal orders edges by (w, min endpoint, max endpoint).
 
 Parity status: every function here is pinned by tests against a library
-routine, a closed form or brute force, except the random-edge sampling,
-whose samples are fixed only by the generator definition; its selection
-rule is pinned by invariants.
+routine, a closed form or brute force.  The random-edge sampling's
+individual draws are fixed only by the generator's definition (published
+known answers pin the generator); their selection rule is pinned by
+invariants and their distribution (uniform and independent over the two
+components, separate per pair and cloud) by statistical tests.
 """
 from __future__ import annotations
 
