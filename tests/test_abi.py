@@ -95,3 +95,33 @@ def test_peaks_library_exports_its_header():
     syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
     for name in names:
         assert name in syms, name
+
+
+def test_knn_limits_and_workspace_queries_on_the_host():
+    # k above 64, k above the requested list length, d < 1 and n >= 2^31 are
+    # rejected; workspace queries (null workspace) launch nothing and grow
+    # with n in every precision
+    L = _lib()
+    lib = L.load()
+    sz = ctypes.c_size_t(0)
+
+    def q(n, d, k, prec, kc=0):
+        sz.value = 0
+        r = lib.famst_knn_graph(None, ctypes.c_int64(n), d, None, 1, k, prec, kc, None, None, None, None,
+                                ctypes.byref(sz), None)
+        return r, sz.value
+
+    assert q(1000, 32, 65, L.FAMST_FP32)[0] == L.FAMST_EINVAL
+    assert q(1000, 32, 40, L.FAMST_BF16, 32)[0] == L.FAMST_EINVAL
+    assert q(1000, 0, 5, L.FAMST_FP32)[0] == L.FAMST_EINVAL
+    assert q(1 << 31, 4, 5, L.FAMST_FP32)[0] == L.FAMST_EINVAL
+    for prec in (L.FAMST_FP32, L.FAMST_BF16, L.FAMST_FP8_E4M3):
+        for d, k in ((32, 10), (128, 64), (960, 20)):
+            sizes = []
+            for n in (1000, 5000, 40000):
+                r, b = q(n, d, k, prec)
+                assert r == L.FAMST_OK, (prec, d, k, n, r)
+                # at least the candidate lists (k' >= k entries of 8 bytes per row)
+                assert b >= n * k * 8
+                sizes.append(b)
+            assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
