@@ -66,6 +66,73 @@ __global__ __launch_bounds__(256) void tree_grad_kernel(const float* __restrict_
   }
 }
 
+// The same sums for d <= 64 NC with d a multiple of 4 and 16-byte aligned
+// rows: lane r holds dimension chunks r, r + 16 of its row (the mapping of
+// sq32_group, so s has the same bits) in registers, each neighbour row is
+// read once as whole chunks, and every element adds the same terms in the
+// same edge order as tree_grad_kernel.
+template <int NC>
+__global__ __launch_bounds__(256) void tree_grad_vec_kernel(const float* __restrict__ X, int d, int64_t n,
+                                                            const int64_t* __restrict__ offs, int B,
+                                                            const int32_t* __restrict__ tu,
+                                                            const int32_t* __restrict__ tv,
+                                                            const uint64_t* __restrict__ skeys,
+                                                            const int64_t* __restrict__ ptr,
+                                                            const float* __restrict__ gW,
+                                                            float* __restrict__ grad) {
+  const int64_t v = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int r16 = threadIdx.x & 15;
+  if (v >= n) return;   // uniform in the 16-lane group
+  const float g = gW[find_cloud(offs, B, v)];
+  const int64_t p0 = ptr[v], p1 = ptr[v + 1];
+  f32x4 a[NC], acc[NC];
+  bool ok[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int t0 = 4 * r16 + 64 * c;
+    ok[c] = t0 < d;
+    a[c] = ok[c] ? *reinterpret_cast<const f32x4*>(X + v * d + t0) : f32x4{0.f, 0.f, 0.f, 0.f};
+    acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int64_t p = p0; p < p1; ++p) {
+    const uint32_t e = (uint32_t)skeys[p];
+    const int o = (tu[e] == v) ? tv[e] : tu[e];
+    f32x4 b[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      b[c] = ok[c] ? *reinterpret_cast<const f32x4*>(X + (int64_t)o * d + 4 * r16 + 64 * c)
+                   : f32x4{0.f, 0.f, 0.f, 0.f};
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (ok[c]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float df = a[c][i] - b[c][i];
+          s = __builtin_fmaf(df, df, s);
+        }
+      }
+    s += __shfl_xor(s, 8, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 1, 16);
+    if (s == 0.f) continue;   // uniform in the group
+    const float w = __builtin_sqrtf(s);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[c][i] += (a[c][i] - b[c][i]) / w;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (ok[c]) {
+      f32x4 r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r[i] = g * acc[c][i];
+      *reinterpret_cast<f32x4*>(grad + v * d + 4 * r16 + 64 * c) = r;
+    }
+}
+
 }  // namespace famst
 
 using namespace famst;
@@ -111,7 +178,13 @@ extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const in
   FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
   if (hbad) return FAMST_EINVAL;
-  FAMST_TRY(launch("mst_backward", tree_grad_kernel, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n,
-                   offs_d, B, tu, tv, skeys, ptr, gW, grad_X));
-  return FAMST_OK;
+  const bool vec = d % 4 == 0 && d <= 128 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(grad_X)) & 15) == 0;
+  if (vec && d <= 64)
+    return launch("mst_backward", tree_grad_vec_kernel<1>, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d,
+                  B, tu, tv, skeys, ptr, gW, grad_X);
+  if (vec)
+    return launch("mst_backward", tree_grad_vec_kernel<2>, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d,
+                  B, tu, tv, skeys, ptr, gW, grad_X);
+  return launch("mst_backward", tree_grad_kernel, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d, B, tu,
+                tv, skeys, ptr, gW, grad_X);
 }

@@ -233,3 +233,34 @@ def test_famst_batched_clouds_k16_per_cloud():
             R = max(len(r.deltas) for r in refs)
             tot = [sum(r.deltas[i] if i < len(r.deltas) else 0 for r in refs) for i in range(R)]
             assert out.deltas[:R] == tot
+
+
+@pytest.mark.parametrize("d", [64, 96, 128])
+def test_gradient_vector_rows_equal_general_kernel_bitwise(d):
+    # rows of d <= 128 (a multiple of 4, 16-byte aligned) take the register
+    # kernel; the same data one float off alignment takes the general kernel:
+    # the two must give the same bits (two clouds, zero-length edges included)
+    print(f"case gradient kernels d={d}", flush=True)
+    rng = np.random.default_rng(d)
+    n, n0 = 5000, 1800
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    par = np.concatenate([[0], rng.integers(0, np.arange(1, n0))]).astype(np.int64)
+    par2 = np.concatenate([[n0], n0 + rng.integers(0, np.arange(1, n - n0))]).astype(np.int64)
+    X[7] = X[par[7]]                                   # a zero-length edge
+    tu = np.concatenate([np.arange(1, n0), np.arange(n0 + 1, n)]).astype(np.int32)
+    tv = np.concatenate([par[1:], par2[1:]]).astype(np.int32)
+    offs = [0, n0, n]
+    gW = torch.tensor([1.5, -0.25], device=DEV)
+    Xa = _dev(X, torch.float32)
+    buf = torch.empty(n * d + 1, dtype=torch.float32, device=DEV)
+    buf[1:] = Xa.reshape(-1)
+    Xm = buf[1:].view(n, d)
+    assert Xa.data_ptr() % 16 == 0 and Xm.data_ptr() % 16 == 4
+    tud, tvd = torch.from_numpy(tu).to(DEV), torch.from_numpy(tv).to(DEV)
+    ga = F.mst_backward(Xa, tud, tvd, gW, offs=offs)
+    gm = F.mst_backward(Xm, tud, tvd, gW, offs=offs)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, gm)
+    ref = np.concatenate([1.5 * oracle.mst_weight_grad(X[:n0], tu[:n0 - 1], tv[:n0 - 1]),
+                          -0.25 * oracle.mst_weight_grad(X[n0:], tu[n0 - 1:] - n0, tv[n0 - 1:] - n0)])
+    np.testing.assert_allclose(ga.cpu().numpy(), ref, atol=2e-5)
