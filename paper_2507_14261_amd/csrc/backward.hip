@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void tree_grad_kernel(const float* __restrict_
   }
 }
 
-// The same sums for d <= 64 NC with d a multiple of 4 and 16-byte aligned
-// rows: lane r holds dimension chunks r, r + 16 of its row (the mapping of
+// The same sums for d <= 64 NC (NC = 1, 2, 4, 8, 16), d a multiple of 4, 16-byte aligned
+// rows: lane r holds dimension chunks r, r + 16, r + 32, ... of its row (the mapping of
 // sq32_group, so s has the same bits) in registers, each neighbour row is
 // read once as whole chunks, and every element adds the same terms in the
 // same edge order as tree_grad_kernel.
@@ -178,13 +178,15 @@ extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const in
   FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
   if (hbad) return FAMST_EINVAL;
-  const bool vec = d % 4 == 0 && d <= 128 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(grad_X)) & 15) == 0;
-  if (vec && d <= 64)
-    return launch("mst_backward", tree_grad_vec_kernel<1>, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d,
-                  B, tu, tv, skeys, ptr, gW, grad_X);
-  if (vec)
-    return launch("mst_backward", tree_grad_vec_kernel<2>, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d,
-                  B, tu, tv, skeys, ptr, gW, grad_X);
+  const bool vec = d % 4 == 0 && d <= 1024 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(grad_X)) & 15) == 0;
+  if (vec) {
+    auto kern = d <= 64 ? tree_grad_vec_kernel<1>
+              : d <= 128 ? tree_grad_vec_kernel<2>
+              : d <= 256 ? tree_grad_vec_kernel<4>
+              : d <= 512 ? tree_grad_vec_kernel<8> : tree_grad_vec_kernel<16>;
+    return launch("mst_backward", kern, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d, B, tu, tv, skeys,
+                  ptr, gW, grad_X);
+  }
   return launch("mst_backward", tree_grad_kernel, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d, B, tu,
                 tv, skeys, ptr, gW, grad_X);
 }

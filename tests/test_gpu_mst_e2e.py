@@ -235,9 +235,9 @@ def test_famst_batched_clouds_k16_per_cloud():
             assert out.deltas[:R] == tot
 
 
-@pytest.mark.parametrize("d", [64, 96, 128])
+@pytest.mark.parametrize("d", [64, 96, 128, 200, 960])
 def test_gradient_vector_rows_equal_general_kernel_bitwise(d):
-    # rows of d <= 128 (a multiple of 4, 16-byte aligned) take the register
+    # rows of d <= 1024 (a multiple of 4, 16-byte aligned) take the register
     # kernel; the same data one float off alignment takes the general kernel:
     # the two must give the same bits (two clouds, zero-length edges included)
     print(f"case gradient kernels d={d}", flush=True)
