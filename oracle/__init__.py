@@ -7,6 +7,6 @@ from .philox import philox4x32_10, seed_key, uniform_index  # noqa: F401
 from .famst import *  # noqa: F401,F403
 from .famst import (EdgeSet, FamstResult, as64, sqdist, sqdist_to, knn_bruteforce,  # noqa: F401
                     knn_exact, undirected_graph, components, random_edges,
-                    refine_edges, refine_edges_literal, canonical_edges, kruskal,
+                    refine_edges, draw_pair_samples, canonical_edges, kruskal,
                     prim_exact, relative_error, famst, famst_batched, final_edges,
                     mst_weight_grad, fd_grad, recall_at_k, DisjointSet)

@@ -9,9 +9,11 @@ the order of the paper's Algorithm 1:
   Phase 1  GetANNs         -> exact k nearest neighbours (Sec. 3, Alg. 1;
                               the paper allows any method that yields the
                               neighbour lists N and distances D)
-  Phase 2  Components      -> Alg. 2 (undirected graph G, DFS components)
-           RandomEdges     -> Alg. 3 (lambda^2 samples per component pair,
-                              keep the lambda shortest)
+  Phase 2  Components      -> Alg. 2 (undirected graph G and its connected
+                              components, computed from the definition of
+                              reachability by minimum-label propagation)
+           RandomEdges     -> Alg. 3 (per component pair, the lambda
+                              shortest of lambda^2 random endpoint pairs)
   Phase 3  RefineEdges     -> Alg. 4, repeated until no edge changes
   Phase 4  GetMST          -> Kruskal on N u E (Sec. 2.1, Sec. 3)
 
@@ -144,41 +146,50 @@ def knn_exact(X, k: int, block: int = 512, margin: int = 16, rows=None):
 
 # ------------------------------------------------- Phase 2: Alg. 2 (graph)
 def undirected_graph(nbr, n: int | None = None):
-    """Alg. 2, first loop: add (i, j) and (j, i) for every j in N[i].  Rows
-    are returned sorted ascending without duplicates or self-loops."""
-    nbr = np.asarray(nbr)
-    n = nbr.shape[0] if n is None else n
-    adj = [set() for _ in range(n)]
-    for i in range(nbr.shape[0]):
-        for j in nbr[i]:
-            j = int(j)
-            adj[i].add(j)
-            adj[j].add(i)
-    return [np.array(sorted(a - {i}), dtype=np.int64) for i, a in enumerate(adj)]
+    """G of Alg. 2: the symmetric closure of the kNN relation, i.e. {i, j}
+    is an edge when j is in N[i] or i is in N[j].  Rows are returned sorted
+    ascending without duplicates or self-loops."""
+    nbr = np.asarray(nbr, dtype=np.int64)
+    m, k = nbr.shape
+    n = m if n is None else n
+    i = np.repeat(np.arange(m, dtype=np.int64), k)
+    j = nbr.reshape(-1)
+    src = np.concatenate([i, j])
+    dst = np.concatenate([j, i])
+    keep = src != dst
+    key = np.unique(src[keep] * n + dst[keep])        # sorted by (row, column), unique
+    rows, cols = key // n, key % n
+    starts = np.searchsorted(rows, np.arange(n + 1))
+    return [cols[starts[r]:starts[r + 1]] for r in range(n)]
 
 
 def components(G):
-    """Alg. 2, DFS part: visit vertices in ascending order; each unvisited
-    vertex starts a new component explored with an explicit stack.
-    Returns (comp int64 [n], comps list of ascending member arrays)."""
+    """Connected components of G (Alg. 2): u and v share a component when a
+    path of G joins them.  Computed from that definition: every vertex starts
+    with its own id as label and repeatedly takes the smallest label among
+    itself and its neighbours.  Labels only shrink and stay ids of the
+    vertex's component, so the iteration stops, and at the fixed point
+    neighbours carry equal labels: each component carries one label, which
+    is its minimum vertex (that vertex can never take a smaller one).
+    Components are numbered by ascending minimum vertex; members are listed
+    ascending.  Returns (comp int64 [n], comps list of member arrays)."""
     n = len(G)
-    visited = np.zeros(n, dtype=bool)
-    comp = np.full(n, -1, dtype=np.int64)
-    comps = []
-    for i in range(n):
-        if visited[i]:
-            continue
-        members = []
-        stack = [i]
-        while stack:
-            u = stack.pop()
-            if not visited[u]:
-                visited[u] = True
-                members.append(u)
-                stack.extend(int(w) for w in G[u] if not visited[w])
-        members = np.array(sorted(members), dtype=np.int64)
-        comp[members] = len(comps)
-        comps.append(members)
+    deg = np.array([len(g) for g in G], dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    dst = np.concatenate([np.asarray(g, dtype=np.int64) for g in G]) if n else np.zeros(0, np.int64)
+    lab = np.arange(n, dtype=np.int64)
+    changed = np.ones(n, dtype=bool)
+    while changed.any():
+        e = changed[src]                                  # only labels that moved can lower others
+        new = lab.copy()
+        np.minimum.at(new, dst[e], lab[src[e]])
+        changed = new < lab
+        lab = new
+    mins, comp = np.unique(lab, return_inverse=True)   # mins ascending -> numbering
+    comp = comp.astype(np.int64)
+    order = np.argsort(comp, kind="stable")            # ascending ids within each component
+    bounds = np.searchsorted(comp[order], np.arange(len(mins) + 1))
+    comps = [order[bounds[c]:bounds[c + 1]] for c in range(len(mins))]
     return comp, comps
 
 
@@ -199,68 +210,59 @@ class EdgeSet:
         return EdgeSet(self.u.copy(), self.v.copy(), self.s.copy(), self.a.copy(), self.b.copy())
 
 
+def draw_pair_samples(comps, a: int, b: int, lam: int, key, cloud: int = 0):
+    """The lambda^2 random endpoint pairs of component pair (a, b) (Alg. 3):
+    sample q takes the first two words (r0, r1) of Philox4x32-10 at counter
+    (a, b, q, cloud) and picks u = C_a[(r0 |C_a|) >> 32], v = C_b[(r1 |C_b|)
+    >> 32], uniformly and independently, with replacement."""
+    Ca, Cb = np.asarray(comps[a]), np.asarray(comps[b])
+    words = np.array([philox4x32_10((a, b, q, cloud), key)[:2] for q in range(lam * lam)],
+                     dtype=np.uint64).reshape(-1, 2)
+    iu = (words[:, 0] * np.uint64(len(Ca))) >> np.uint64(32)
+    iv = (words[:, 1] * np.uint64(len(Cb))) >> np.uint64(32)
+    return Ca[iu.astype(np.int64)].astype(np.int64), Cb[iv.astype(np.int64)].astype(np.int64)
+
+
 def random_edges(X, comps, lam: int, seed: int, cloud: int = 0, pairs=None) -> EdgeSet:
-    """Alg. 3: for every component pair a < b draw lambda^2 endpoint pairs
-    (u from C_a, v from C_b), sort them by distance (stable) and keep the
-    first lambda.  Edges are listed in (a, b, rank) order.  ``pairs``
-    restricts the work to the given (a, b) pairs, in the given order: every
-    pair's draws come from its own counters, so a subset is computed exactly
-    as in the full run."""
+    """Alg. 3: the edges of component pair a < b are the lambda samples with
+    the smallest (s, q) among its lambda^2 draws (draw_pair_samples), listed
+    in that order -- the stable sort by distance of the paper's listing, cut
+    after lambda.  Pairs are listed in (a, b) order.  ``pairs`` restricts the
+    work to the given (a, b) pairs, in the given order: every pair's draws
+    come from its own counters, so a subset is computed exactly as in the
+    full run."""
     X64 = as64(X)
     key = seed_key(seed)
     t = len(comps)
     if pairs is None:
         pairs = [(a, b) for a in range(t - 1) for b in range(a + 1, t)]
-    out_u, out_v, out_s, out_a, out_b = [], [], [], [], []
+    parts = []
     for a, b in pairs:
-        Ca, Cb = comps[a], comps[b]
-        cands = []
-        for sample in range(lam * lam):
-            r = philox4x32_10((a, b, sample, cloud), key)
-            u = int(Ca[uniform_index(r[0], len(Ca))])
-            v = int(Cb[uniform_index(r[1], len(Cb))])
-            cands.append((sqdist(X64, u, v), u, v))
-        cands.sort(key=lambda c: c[0])          # stable: ties keep sample order
-        for s, u, v in cands[:lam]:
-            out_u.append(u), out_v.append(v), out_s.append(s)
-            out_a.append(a), out_b.append(b)
-    i64 = lambda x: np.array(x, dtype=np.int64)
-    return EdgeSet(i64(out_u), i64(out_v), np.array(out_s, dtype=np.float64), i64(out_a), i64(out_b))
+        u, v = draw_pair_samples(comps, a, b, lam, key, cloud)
+        diff = X64[u] - X64[v]
+        s = np.einsum("ij,ij->i", diff, diff)
+        keep = np.lexsort((np.arange(len(s)), s))[:lam]    # smallest (s, q)
+        parts.append((u[keep], v[keep], s[keep], np.full(lam, a), np.full(lam, b)))
+    if not parts:
+        z = np.zeros(0, dtype=np.int64)
+        return EdgeSet(z, z.copy(), np.zeros(0), z.copy(), z.copy())
+    cat = [np.concatenate([p[i] for p in parts]) for i in range(5)]
+    return EdgeSet(cat[0].astype(np.int64), cat[1].astype(np.int64), cat[2].astype(np.float64),
+                   cat[3].astype(np.int64), cat[4].astype(np.int64))
 
 
 # ------------------------------------------------ Phase 3: Alg. 4 (refine)
-def refine_edges_literal(X, G, comp, E: EdgeSet):
-    """Alg. 4 written out loop by loop (for small inputs)."""
-    X64 = as64(X)
-    R = E.copy()
-    delta = 0
-    for e in range(len(E)):
-        u, v, d, a, b = int(E.u[e]), int(E.v[e]), float(E.s[e]), int(E.a[e]), int(E.b[e])
-        us, vs, ds = u, v, d
-        Nu = [int(w) for w in G[u] if comp[w] == a]
-        Nv = [int(w) for w in G[v] if comp[w] == b]
-        for up in Nu:
-            if up != v:
-                dp = sqdist(X64, up, v)
-                if dp < ds:
-                    us, ds = up, dp
-        for vp in Nv:
-            if vp != u:
-                dp = sqdist(X64, us, vp)
-                if dp < ds:
-                    vs, ds = vp, dp
-        if (us, vs) != (u, v):
-            delta += 1
-        R.u[e], R.v[e], R.s[e] = us, vs, ds
-    return R, delta
-
-
 def refine_edges(X, G, comp, E: EdgeSet):
     """Alg. 4, one round.  Each edge only reads X, G and its own endpoints,
-    so edges are independent.  A scan in ascending order with a strict "<"
-    ends at the first index attaining the minimum when that minimum beats
-    the incumbent, which is what argmin returns; this vectorised form is
-    checked against refine_edges_literal in the tests."""
+    so edges are independent.  For edge (u, v) of pair (a, b):
+      u* = the neighbour u' of u with comp(u') = a, u' != v that has the
+           smallest (s(u', v), u'), taken only if s(u', v) < s(u, v);
+      v* = the neighbour v' of v with comp(v') = b, v' != u that has the
+           smallest (s(u*, v'), v'), taken only if it beats the length after
+           the first step.
+    This is what the paper's scans in ascending id with a strict "<" end
+    at: the first index attaining the minimum, when that minimum beats the
+    incumbent (argmin returns the first index)."""
     X64 = as64(X)
     R = E.copy()
     delta = 0
@@ -310,19 +312,18 @@ class DisjointSet:
 
 def canonical_edges(eu, ev, w):
     """Edges as (min, max, w) with duplicates on (min, max) removed (the
-    first occurrence's weight is kept) and self-loops dropped."""
-    seen = {}
-    for a, b, x in zip(np.asarray(eu).tolist(), np.asarray(ev).tolist(), np.asarray(w).tolist()):
-        if a == b:
-            continue
-        key = (a, b) if a < b else (b, a)
-        if key not in seen:
-            seen[key] = float(x)
-    keys = sorted(seen)
-    lo = np.array([k[0] for k in keys], dtype=np.int64)
-    hi = np.array([k[1] for k in keys], dtype=np.int64)
-    ww = np.array([seen[k] for k in keys], dtype=np.float64)
-    return lo, hi, ww
+    first occurrence's weight is kept) and self-loops dropped; returned in
+    ascending (min, max) order."""
+    eu, ev = np.asarray(eu, dtype=np.int64), np.asarray(ev, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    lo, hi = np.minimum(eu, ev), np.maximum(eu, ev)
+    pos = np.flatnonzero(lo != hi)
+    lo, hi, w = lo[pos], hi[pos], w[pos]
+    order = np.lexsort((np.arange(len(lo)), hi, lo))   # by (min, max), then first occurrence
+    lo, hi, w = lo[order], hi[order], w[order]
+    first = np.ones(len(lo), dtype=bool)
+    first[1:] = (lo[1:] != lo[:-1]) | (hi[1:] != hi[:-1])
+    return lo[first], hi[first], w[first]
 
 
 def kruskal(n: int, eu, ev, w):

@@ -231,3 +231,11 @@ def test_famst_degenerate_inputs_closed_forms():
     # identical points: every distance is zero
     r = oracle.famst(np.ones((50, 4)), 3, 2)
     assert r.W == 0.0 and len(r.tu) == 49 and r.spanning
+
+
+def test_canonical_edges_first_occurrence_and_order():
+    # (min, max) keys, self-loops dropped, the first occurrence's weight kept,
+    # output in ascending (min, max) order
+    lo, hi, w = oracle.canonical_edges([3, 1, 2, 0, 2, 3, 4], [1, 3, 0, 2, 2, 0, 1], [5.0, 7.0, 1.0, 2.0, 9.0, 4.0, 3.0])
+    assert lo.tolist() == [0, 0, 1, 1] and hi.tolist() == [2, 3, 3, 4]
+    assert w.tolist() == [1.0, 4.0, 5.0, 3.0]

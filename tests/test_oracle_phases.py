@@ -35,6 +35,42 @@ def test_components_match_scipy(k):
     assert comp[0] == 0
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_components_match_reachability_closure(seed):
+    # brute force on small random graphs: u and v share a component exactly
+    # when the transitive closure of the adjacency matrix joins them
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 40))
+    nbr = rng.integers(0, n, size=(n, 1))
+    keep = rng.random(n) < 0.7
+    nbr[~keep, 0] = np.flatnonzero(~keep)          # self entries add no edge
+    G = oracle.undirected_graph(nbr)
+    R = np.eye(n, dtype=bool)
+    for i in range(n):
+        R[i, G[i]] = True
+    for _ in range(n):
+        R = (R.astype(np.int64) @ R.astype(np.int64)) > 0
+    comp, comps = oracle.components(G)
+    for u in range(n):
+        for v in range(n):
+            assert (comp[u] == comp[v]) == R[u, v]
+    mins = [int(R[i].argmax()) for i in range(n)]  # smallest vertex reachable from i
+    order = sorted(set(mins))
+    assert [order.index(m) for m in mins] == comp.tolist()
+
+
+def test_components_long_path_shuffled_ids():
+    # a path whose ids are shuffled: the smallest id must travel the whole path
+    rng = np.random.default_rng(7)
+    n = 3000
+    ids = rng.permutation(n)
+    nbr = np.empty((n, 1), dtype=np.int64)
+    nbr[ids[:-1], 0] = ids[1:]
+    nbr[ids[-1], 0] = ids[-2]
+    comp, comps = oracle.components(oracle.undirected_graph(nbr))
+    assert len(comps) == 1 and np.all(comp == 0) and np.array_equal(comps[0], np.arange(n))
+
+
 def test_undirected_graph_symmetric_sorted():
     nbr = np.array([[1, 2], [0, 2], [0, 1], [0, 1]])
     G = oracle.undirected_graph(nbr)
@@ -148,18 +184,45 @@ def test_refine_strict_less_keeps_incumbent_on_tie():
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_refine_vectorised_equals_literal(seed):
+def test_refine_round_properties(seed):
+    # one round of Alg. 4 stated as properties of each output edge, checked
+    # by enumerating the neighbours: u* is u or a same-component neighbour of
+    # u other than v, no such neighbour is strictly closer to v than u*, and
+    # among equally close ones u* has the smallest id (likewise v* from u*,
+    # skipping the original u); a move happens only on a strict decrease
     X = datagen.blobs(n=500, d=5, n_clusters=4, seed=seed)
     nbr, _ = oracle.knn_exact(X, 2)
     G = oracle.undirected_graph(nbr)
     comp, comps = oracle.components(G)
     E = oracle.random_edges(X, comps, 3, seed=seed)
+    X64 = oracle.as64(X)
     for _ in range(4):
-        A, da = oracle.refine_edges(X, G, comp, E)
-        B, db = oracle.refine_edges_literal(X, G, comp, E)
-        assert da == db
-        assert np.array_equal(A.u, B.u) and np.array_equal(A.v, B.v) and np.array_equal(A.s, B.s)
-        E = A
+        R, delta = oracle.refine_edges(X, G, comp, E)
+        moved = 0
+        for e in range(len(E)):
+            u, v, s0 = int(E.u[e]), int(E.v[e]), float(E.s[e])
+            us, vs, s1 = int(R.u[e]), int(R.v[e]), float(R.s[e])
+            cu = [int(w) for w in G[u] if comp[w] == E.a[e] and w != v]
+            su = {w: oracle.sqdist(X64, w, v) for w in cu}
+            if us == u:
+                assert all(x >= s0 for x in su.values())
+                mid = s0
+            else:
+                assert us in su and su[us] < s0
+                assert all(x > su[us] or (x == su[us] and w >= us) for w, x in su.items())
+                mid = su[us]
+            cv = [int(w) for w in G[v] if comp[w] == E.b[e] and w != u]
+            sv = {w: oracle.sqdist(X64, us, w) for w in cv}
+            if vs == v:
+                assert all(x >= mid for x in sv.values())
+                assert s1 == mid
+            else:
+                assert vs in sv and sv[vs] < mid and s1 == sv[vs]
+                assert all(x > sv[vs] or (x == sv[vs] and w >= vs) for w, x in sv.items())
+            assert s1 == oracle.sqdist(X64, us, vs)
+            moved += (us, vs) != (u, v)
+        assert moved == delta
+        E = R
 
 
 def test_refine_invariants_and_local_optimality():
@@ -187,8 +250,8 @@ def test_refine_invariants_and_local_optimality():
                 assert oracle.sqdist(X64, u, int(vp)) >= s
 
 
-@pytest.mark.parametrize("fn", [oracle.refine_edges, oracle.refine_edges_literal])
-def test_refine_tie_among_neighbours_takes_smaller_id(fn):
+def test_refine_tie_among_neighbours_takes_smaller_id():
+    fn = oracle.refine_edges
     # u=0 at x=0; its neighbours 1 and 2 sit at the same distance from v=3
     X = np.array([[0.0, 0.0], [5.0, 1.0], [5.0, -1.0], [10.0, 0.0]], dtype=np.float32)
     G = [np.array([1, 2]), np.array([0]), np.array([0]), np.array([], dtype=np.int64)]
@@ -198,8 +261,8 @@ def test_refine_tie_among_neighbours_takes_smaller_id(fn):
     assert delta == 1 and int(R.u[0]) == 1 and float(R.s[0]) == 26.0
 
 
-@pytest.mark.parametrize("fn", [oracle.refine_edges, oracle.refine_edges_literal])
-def test_refine_equal_to_incumbent_not_taken(fn):
+def test_refine_equal_to_incumbent_not_taken():
+    fn = oracle.refine_edges
     X = np.array([[0.0], [2.0], [1.0]], dtype=np.float32)
     G = [np.array([1]), np.array([0]), np.array([], dtype=np.int64)]
     comp = np.array([0, 0, 1])
