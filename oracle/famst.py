@@ -101,12 +101,20 @@ def knn_exact(X, k: int, block: int = 512, margin: int = 16, rows=None):
     """Exact k nearest neighbours (Phase 1 of Alg. 1 with an exact search).
 
     Candidates are screened with the float64 expansion |x|^2+|y|^2-2x.y
-    (one matrix product per row block), the k+margin best are recomputed by
-    direct difference and ordered by (s, j).  The screen is verified: every
-    non-candidate must exceed the k-th exact value by more than the
-    expansion's rounding bound, otherwise the row is redone by direct
-    difference over all points.  ``rows`` restricts the query rows.
+    (one matrix product per row block) and the k+margin smallest screened
+    values of each row are taken; they are recomputed by direct difference
+    and ordered by (s, j).  The screen is verified: every non-candidate must
+    exceed the k-th exact value by more than the expansion's rounding bound,
+    otherwise the row is redone by direct difference over all points.
+    ``rows`` restricts the query rows.
     Returns (nbr int64 [m, k], s float64 [m, k]) with s squared distances.
+
+    Selecting the k+margin smallest of a row: the (k+margin)-th smallest
+    value of any subset of the row's columns is at least the (k+margin)-th
+    smallest of the whole row, so every one of the row's k+margin smallest
+    values lies at or below it.  The subset is every stride-th column
+    (all columns when n <= 32768); the values at or below its threshold
+    are then partitioned exactly.
     """
     X64 = as64(X)
     n, d = X64.shape
@@ -117,18 +125,33 @@ def knn_exact(X, k: int, block: int = 512, margin: int = 16, rows=None):
     max_norm = float(norms.max())
     gamma = 2.0 * (d + 4) * U64
     kc = min(n - 1, k + margin)
+    stride = max(1, n // 32768)
     nbr = np.empty((len(rows), k), dtype=np.int64)
     sq = np.empty((len(rows), k), dtype=np.float64)
+    S_buf = np.empty((min(block, len(rows)), n))          # reused: no large allocation per block
+    M_buf = np.empty(S_buf.shape, dtype=bool)
     for s0 in range(0, len(rows), block):
         rb = rows[s0:s0 + block]
-        S = norms[rb, None] + norms[None, :] - 2.0 * (X64[rb] @ X64.T)
+        S = S_buf[:len(rb)]
+        np.matmul(X64[rb], X64.T, out=S)
+        S *= -2.0
+        S += norms[None, :]
+        S += norms[rb, None]
         S[np.arange(len(rb)), rb] = np.inf
         if kc < n - 1:
-            cand = np.argpartition(S, kc - 1, axis=1)[:, :kc]
+            thr = np.partition(S[:, ::stride], kc - 1, axis=1)[:, kc - 1]
+            M = M_buf[:len(rb)]
+            np.less_equal(S, thr[:, None], out=M)
+            rr, cc = np.nonzero(M)
+            bounds = np.searchsorted(rr, np.arange(len(rb) + 1))
         else:
             cand = np.argsort(S, axis=1)[:, :n - 1]
         for r, i in enumerate(rb):
-            c = cand[r]
+            if kc < n - 1:
+                c = cc[bounds[r]:bounds[r + 1]]
+                c = c[np.argpartition(S[r, c], kc - 1)[:kc]]
+            else:
+                c = cand[r]
             s_c = sqdist_to(X64, i, c)
             order = np.lexsort((c, s_c))
             sel, s_sel = c[order[:k]], s_c[order[:k]]
