@@ -226,6 +226,28 @@ int famst_mst_backward(const float* X, int64_t n, int32_t d,
                        void* ws, size_t* ws_bytes, void* stream);
 
 /*
+ * famst_mst_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the workspace taken from
+ * a fixed device array of FAMST_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends.  The call allocates
+ * nothing; the caller still provides X, tu, tv, gW and grad_X, and the
+ * current device must be the one that owns them and the stream.
+ *   scratch_needed  host, may be NULL: the workspace bytes this call needs
+ * Errors: as famst_mst_backward; FAMST_ECAPACITY when the call needs more
+ * than FAMST_NOALLOC_SCRATCH_BYTES (about one million points: the bytes
+ * grow as 64 n), with *scratch_needed set and nothing queued.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the
+ * same GPU (other streams, other host threads) race and must be ordered by
+ * the caller.  The stream is synchronised, as in famst_mst_backward.
+ */
+#define FAMST_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int famst_mst_backward_noalloc(const float* X, int64_t n, int32_t d,
+                               const int64_t* offs, int32_t B,
+                               const int32_t* tu, const int32_t* tv, const float* gW,
+                               float* grad_X, size_t* scratch_needed, void* stream);
+
+/*
  * Exact tree weight and its gradient for a batch of clouds in one
  * persistent launch (FAMST with k = n_b - 1 is the exact minimum spanning
  * tree, Sec. 2.1 / Prim).  Blocks take clouds from a work queue, largest

@@ -12,5 +12,6 @@ C-ABI (include/famst.h); this package only marshals arguments:
     MSTWeight     torch.autograd.Function around famst + mst_backward
 """
 from .api import (Edges, FamstOut, Graph, MSTWeight, connect, famst, knn_graph, mst,  # noqa: F401
-                  mst_backward, mst_dense_fused, profile_enable, profile_read, profile_reset, refine)
+                  mst_backward, mst_backward_noalloc, mst_dense_fused, profile_enable, profile_read,
+                  profile_reset, refine)
 from ._lib import FamstError, load  # noqa: F401

@@ -26,10 +26,11 @@ FAMST_KRUSKAL = 1
 FAMST_DENSE_PRIM = 2
 
 FAMST_NSTATS = 8
+FAMST_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "famst_strerror", "famst_version", "famst_knn_graph", "famst_connect", "famst_refine",
-    "famst_mst", "famst_mst_backward", "famst_mst_dense_fused", "famst_profile_enable", "famst_profile_reset",
+    "famst_mst", "famst_mst_backward", "famst_mst_backward_noalloc", "famst_mst_dense_fused", "famst_profile_enable", "famst_profile_reset",
     "famst_profile_read",
 ]
 
@@ -74,6 +75,8 @@ def load():
     lib.famst_mst.argtypes = [P, I64, I32, PI64, I32, P, P, I32, P, P, P, I64, I32, P, P, P, P, P, PSZ, P]
     lib.famst_mst_backward.restype = ctypes.c_int
     lib.famst_mst_backward.argtypes = [P, I64, I32, PI64, I32, P, P, P, P, P, PSZ, P]
+    lib.famst_mst_backward_noalloc.restype = ctypes.c_int
+    lib.famst_mst_backward_noalloc.argtypes = [P, I64, I32, PI64, I32, P, P, P, P, PSZ, P]
     lib.famst_mst_dense_fused.restype = ctypes.c_int
     lib.famst_mst_dense_fused.argtypes = [P, I64, I32, PI64, I32, P, P, P, P, P, P, PSZ, P]
     lib.famst_profile_enable.restype = ctypes.c_int

@@ -208,6 +208,24 @@ def mst_backward(X, tu, tv, gW, offs=None):
     return grad
 
 
+def mst_backward_noalloc(X, tu, tv, gW, offs=None, grad=None):
+    """mst_backward on the library's fixed scratch array (no workspace is
+    allocated by the call; ``grad`` may be given to allocate nothing at
+    all).  Returns (grad, scratch bytes the call needed)."""
+    lib = L.load()
+    X = _dev(X, torch.float32, "X")
+    n, d = X.shape
+    o, B = _offs(offs, n)
+    gW = _dev(gW.reshape(-1).to(torch.float32), torch.float32, "gW")
+    grad = torch.empty_like(X) if grad is None else _dev(grad, torch.float32, "grad")
+    need = ctypes.c_size_t(0)
+    code = lib.famst_mst_backward_noalloc(_ptr(X), n, d, _offs_ptr(o), B, _ptr(_dev(tu, torch.int32, "tu")),
+                                          _ptr(_dev(tv, torch.int32, "tv")), _ptr(gW), _ptr(grad),
+                                          ctypes.byref(need), _stream())
+    L.check(code, "famst_mst_backward_noalloc")
+    return grad, int(need.value)
+
+
 def mst_dense_fused(X, offs=None):
     """Exact tree of every cloud, its weight and the gradient in one
     persistent launch.  Returns (tu, tv, tw, W, G) with G = dW/dX."""

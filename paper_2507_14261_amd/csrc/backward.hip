@@ -3,6 +3,8 @@
 // tree held fixed: every edge adds its unit direction (x_i - x_j)/|x_i - x_j|
 // to row i and the opposite to row j.  Rows gather their incident edges in
 // ascending edge order, so the sums are deterministic.
+#include <mutex>
+
 #include "famst_common.hpp"
 #include "prims.hpp"
 
@@ -167,7 +169,7 @@ extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const in
   if (!X || !tu || !tv || !gW || !grad_X) return FAMST_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
-  FAMST_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  FAMST_TRY(fill_i32(bad, 0, 1, s));
   FAMST_TRY(fill_i64(deg, 0, n + 1, s));
   FAMST_TRY(launch("incid_keys", incid_keys_kernel, dim3(cdiv(m, 256)), dim3(256), 0, s, tu, tv, m, n,
                    keys, deg, bad));
@@ -189,4 +191,43 @@ extern "C" int famst_mst_backward(const float* X, int64_t n, int32_t d, const in
   }
   return launch("mst_backward", tree_grad_kernel, dim3(cdiv(n, 16)), dim3(256), 0, s, X, d, n, offs_d, B, tu,
                 tv, skeys, ptr, gW, grad_X);
+}
+
+// ------------------------------------------------ allocation-free variant
+// The workspace of famst_mst_backward lives in a file-scope device array.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is looked up once per device with hipGetSymbolAddress
+// (with that device current) and only that address reaches the kernels.
+namespace famst {
+static __device__ __align__(256) char scratch[FAMST_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  FAMST_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FAMST_ENOTIMPL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FAMST_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FAMST_OK;
+}
+}  // namespace famst
+
+extern "C" int famst_mst_backward_noalloc(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
+                                          int32_t B, const int32_t* tu, const int32_t* tv, const float* gW,
+                                          float* grad_X, size_t* scratch_needed, void* stream) {
+  size_t need = 0;
+  FAMST_TRY(famst_mst_backward(X, n, d, offs_h, B, tu, tv, gW, grad_X, nullptr, &need, stream));
+  if (scratch_needed) *scratch_needed = need;
+  if (need > FAMST_NOALLOC_SCRATCH_BYTES) return FAMST_ECAPACITY;
+  if (!X || !tu || !tv || !gW || !grad_X) return FAMST_EINVAL;
+  void* ws = nullptr;
+  FAMST_TRY(scratch_address(&ws));
+  return famst_mst_backward(X, n, d, offs_h, B, tu, tv, gW, grad_X, ws, &need, stream);
 }

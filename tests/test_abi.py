@@ -125,3 +125,29 @@ def test_knn_limits_and_workspace_queries_on_the_host():
                 assert b >= n * k * 8
                 sizes.append(b)
             assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+
+
+def test_noalloc_gradient_limits_on_the_host():
+    # the allocation-free gradient validates its arguments and its scratch
+    # limit before touching any device: sizes beyond the fixed array return
+    # ECAPACITY with the bytes needed, null pointers EINVAL
+    L = _lib()
+    lib = L.load()
+    need = ctypes.c_size_t(0)
+    assert lib.famst_mst_backward_noalloc(None, 4_000_000, 8, None, 1, None, None, None, None,
+                                          ctypes.byref(need), None) == L.FAMST_ECAPACITY
+    assert need.value > L.FAMST_NOALLOC_SCRATCH_BYTES
+    need.value = 0
+    assert lib.famst_mst_backward_noalloc(None, 1000, 8, None, 1, None, None, None, None,
+                                          ctypes.byref(need), None) == L.FAMST_EINVAL
+    assert 0 < need.value <= L.FAMST_NOALLOC_SCRATCH_BYTES
+    offs = (ctypes.c_int64 * 3)(0, 1, 100)   # a one-point cloud
+    assert lib.famst_mst_backward_noalloc(None, 100, 4, offs, 2, None, None, None, None, None,
+                                          None) == L.FAMST_EINVAL
+    # the largest single cloud the array serves, from the size query
+    lo, hi = 1000, 4_000_000
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lib.famst_mst_backward_noalloc(None, mid, 8, None, 1, None, None, None, None, ctypes.byref(need), None)
+        lo, hi = (mid, hi) if need.value <= L.FAMST_NOALLOC_SCRATCH_BYTES else (lo, mid)
+    assert lo >= 1_000_000
