@@ -116,7 +116,10 @@ int famst_version(void);   /* major * 10000 + minor * 100 + patch */
  *   stats    host int64 [FAMST_NSTATS] or NULL; if given the stream is
  *            synchronised and the counters above are stored
  * Errors: EINVAL, ENONFINITE (checked on the device; the stream is then
- * synchronised), EWORKSPACE, EHIP.
+ * synchronised), EWORKSPACE, EHIP; ECAPACITY in exact mode when more than
+ * 2048 points of a cloud lie within float32 rounding of a recomputed row's
+ * k-th distance (massive exact ties); ENOTIMPL when a launch would exceed
+ * 2^32 - 1 work-items.
  */
 int famst_knn_graph(const float* X, int64_t n, int32_t d,
                     const int64_t* offs, int32_t B,

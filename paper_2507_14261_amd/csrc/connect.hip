@@ -154,7 +154,8 @@ __device__ __forceinline__ int64_t pair_start(int64_t a, int64_t t) {
   return a * t - a * (a + 1) / 2;
 }
 
-// One wave per component pair: lambda^2 samples drawn with Philox, their
+// One wave per component pair (pairs taken with a stride of the grid):
+// lambda^2 samples drawn with Philox, their
 // float32 distances, and the lambda smallest by (s, sample).
 // CAP >= lambda^2 sample slots in LDS: 64 for lambda <= 8 (small enough for
 // many resident waves), 1024 up to lambda = 32.
@@ -163,11 +164,11 @@ __global__ __launch_bounds__(64) void lambda_edges_kernel(
     const float* __restrict__ X, int d, const CloudPairs* __restrict__ cp, int B, int lam,
     uint32_t key0, uint32_t key1, const int32_t* __restrict__ members,
     const int64_t* __restrict__ comp_ptr, int32_t* __restrict__ eu, int32_t* __restrict__ ev,
-    float* __restrict__ ew, int32_t* __restrict__ ea, int32_t* __restrict__ eb) {
+    float* __restrict__ ew, int32_t* __restrict__ ea, int32_t* __restrict__ eb, int64_t P) {
   __shared__ SelectSmem<CAP> sm;
   __shared__ int su[CAP], sv[CAP];
-  const int64_t p = blockIdx.x;
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  for (int64_t p = blockIdx.x; p < P; p += gridDim.x) {
   // cloud of this pair
   int cb = 0;
   {
@@ -221,6 +222,8 @@ __global__ __launch_bounds__(64) void lambda_edges_kernel(
       ea[o] = (int32_t)A;
       eb[o] = (int32_t)Bc;
     }
+  }
+  __syncthreads();   // the next pair reuses the LDS lists
   }
 }
 
@@ -343,9 +346,9 @@ extern "C" int famst_connect(const float* X, int64_t n, int32_t d, const int64_t
   if (P > 0) {
     FAMST_HIP(hipMemcpyAsync(cp, hcp.data(), sizeof(CloudPairs) * B, hipMemcpyHostToDevice, s));
     auto kern = lambda * lambda <= 64 ? lambda_edges_kernel<64> : lambda_edges_kernel<1024>;
-    FAMST_TRY(launch("lambda_edges", kern, dim3((unsigned)P), dim3(64), 0, s, X, d, cp, B, lambda,
+    FAMST_TRY(launch("lambda_edges", kern, dim3(stride_grid(P)), dim3(64), 0, s, X, d, cp, B, lambda,
                      (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), members, comp_ptr, eu, ev,
-                     ew, ea, eb));
+                     ew, ea, eb, P));
   }
   FAMST_HIP(hipStreamSynchronize(s));
   return FAMST_OK;

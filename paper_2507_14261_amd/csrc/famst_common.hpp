@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -60,6 +62,9 @@ template <class K, class... Args>
 inline int launch(const char* name, K kernel, dim3 grid, dim3 block, size_t lds,
                   hipStream_t s, Args... args) {
   if (grid.x == 0 || grid.y == 0 || grid.z == 0) return FAMST_OK;
+  // a dispatch holds fewer than 2^32 work-items
+  if ((uint64_t)grid.x * grid.y * grid.z * block.x * block.y * block.z >= (uint64_t(1) << 32))
+    return FAMST_ENOTIMPL;
   prof_begin(name, s);
   hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
   hipError_t e = hipGetLastError();
@@ -68,6 +73,11 @@ inline int launch(const char* name, K kernel, dim3 grid, dim3 block, size_t lds,
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Grid of a kernel that loops over its work units with a stride of the grid:
+// enough blocks to fill the chip many times over, far below the dispatch limit.
+constexpr int64_t kMaxStrideBlocks = int64_t(1) << 20;
+inline unsigned stride_grid(int64_t units) { return (unsigned)std::min<int64_t>(units, kMaxStrideBlocks); }
 
 // ------------------------------------------------------- device helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

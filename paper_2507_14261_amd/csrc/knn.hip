@@ -778,7 +778,8 @@ __global__ __launch_bounds__(256, (KC == 32 ? 2 : 1)) void dist_topk_kc_kernel(
 }
 
 // ------------------------------------------------------------- re-rank
-// One wave per row: direct-difference float32 distances of the KC
+// One wave per row (rows taken with a stride of the grid): direct-difference
+// float32 distances of the KC
 // candidates, selection of the k smallest by (s, j) with float64 at a
 // near-tie boundary, and the certificate that no non-candidate is closer.
 struct RerankArgs {
@@ -806,8 +807,10 @@ struct RerankArgs {
 
 __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
   __shared__ SelectSmem<64> sm;
-  const int64_t q = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+  __shared__ int invalid;
   const int t = threadIdx.x;
+  for (int64_t qi = blockIdx.x; qi < a.n; qi += gridDim.x) {
+  const int64_t q = a.order ? (int64_t)a.order[qi] : qi;
   const int cb = find_cloud(a.offs, a.B, q);
   const int64_t nb = a.offs[cb + 1] - a.offs[cb];
   const int Lmax = (int)min<int64_t>(a.KC, nb - 1);
@@ -817,7 +820,6 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
   // slots the screening never filled hold (+inf, INT_MAX) and sort last
   const int jraw = t < Lmax ? a.cand_j[q * a.KC + t] : 0x7FFFFFFF;
   int L = __builtin_popcountll(ballot(jraw != 0x7FFFFFFF));
-  __shared__ int invalid;
   if (t == 0) invalid = 0;
   __syncthreads();
   const int need = (int)min<int64_t>(a.k, nb - 1);
@@ -871,6 +873,8 @@ __global__ __launch_bounds__(64) void rerank_kernel(RerankArgs a) {
     }
     a.bad_flag[q] = (!cert || invalid) ? 1 : 0;
   }
+  __syncthreads();   // the next row reuses the LDS lists
+  }
 }
 
 // The uncertified rows, in ascending order, at their exclusive-scan
@@ -884,8 +888,55 @@ __global__ __launch_bounds__(256) void list_flagged_kernel(const int64_t* __rest
 }
 
 // Exact recomputation of a row: collect every point whose float32 distance
-// is within the bound of the current k-th, then select as above.
+// is within the bound of the current k-th, then select as above.  When more
+// than FB_CAP points lie under that bound (the screened candidates were far
+// from the true neighbours), the k-th smallest float32 distance of the row is
+// found exactly by a radix select over its bits (squared distances are
+// nonnegative, so their bit patterns order like the values: three histogram
+// passes of 11, 11 and 10 bits, with sm.rank as the 2048 bins), and the
+// points are collected again under that value's near-tie bound.
 constexpr int FB_CAP = 2048;
+
+__device__ __forceinline__ float row_kth_radix(SelectSmem<FB_CAP>& sm, const float* __restrict__ X, int d,
+                                               const float* __restrict__ xq, int64_t q, int64_t c0,
+                                               int64_t c1, int k) {
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  uint32_t prefix = 0, pmask = 0;
+  int rem = k;   // rank of the wanted value among those matching the prefix (1-based)
+  const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = shifts[pass];
+    const uint32_t dmask = (1u << widths[pass]) - 1u;
+    for (int b = t; b < FB_CAP; b += 256) sm.rank[b] = 0;
+    __syncthreads();
+    for (int64_t j0 = c0; j0 < c1; j0 += 16) {
+      const int64_t j = j0 + grp;
+      if (j < c1 && j != q) {
+        const uint32_t bits = __float_as_uint(sq32_group(xq, X + j * d, d, r16));
+        if (r16 == 0 && (bits & pmask) == prefix) atomicAdd(&sm.rank[(bits >> sh) & dmask], 1);
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      int cum = 0, sel = (int)dmask;
+      for (int b = 0; b <= (int)dmask; ++b) {
+        if (cum + sm.rank[b] >= rem) {
+          sel = b;
+          break;
+        }
+        cum += sm.rank[b];
+      }
+      sm.cnt[2] = sel;
+      sm.cnt[3] = rem - cum;
+    }
+    __syncthreads();
+    prefix |= (uint32_t)sm.cnt[2] << sh;
+    pmask |= dmask << sh;
+    rem = sm.cnt[3];
+    __syncthreads();
+  }
+  return __uint_as_float(prefix);
+}
 
 __global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict__ X, int d,
                                                         const int64_t* __restrict__ offs, int B,
@@ -893,47 +944,57 @@ __global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict_
                                                         const float* __restrict__ kth_s,
                                                         int* __restrict__ nbr, float* __restrict__ dist,
                                                         unsigned long long* __restrict__ counters,
-                                                        int* __restrict__ overflow) {
+                                                        int* __restrict__ overflow, int64_t nrows) {
   __shared__ SelectSmem<FB_CAP> sm;
   __shared__ int cnt;
-  const int64_t q = rows[blockIdx.x];
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  for (int64_t ri = blockIdx.x; ri < nrows; ri += gridDim.x) {
+  const int64_t q = rows[ri];
   const int cb = find_cloud(offs, B, q);
   const int64_t c0 = offs[cb], c1 = offs[cb + 1];
   const float tau = tau32(d);
-  const float T = kth_s[q] * (1.0f + 2.0f * tau) * (1.0f + 2.0f * tau);
+  const float up2 = (1.0f + 2.0f * tau) * (1.0f + 2.0f * tau);
+  float T = kth_s[q] * up2;
   const float* xq = X + q * d;
-  if (t == 0) cnt = 0;
-  __syncthreads();
-  for (int64_t j0 = c0; j0 < c1; j0 += 16) {
-    int64_t j = j0 + grp;
-    float v = F_INF;
-    if (j < c1 && j != q) v = sq32_group(xq, X + j * d, d, r16);
-    if (r16 == 0 && v <= T) {
-      int p = atomicAdd(&cnt, 1);
-      if (p < FB_CAP) {
-        sm.s[p] = v;
-        sm.id[p] = (int)j;
+  int L = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (t == 0) cnt = 0;
+    __syncthreads();
+    for (int64_t j0 = c0; j0 < c1; j0 += 16) {
+      int64_t j = j0 + grp;
+      float v = F_INF;
+      if (j < c1 && j != q) v = sq32_group(xq, X + j * d, d, r16);
+      if (r16 == 0 && v <= T) {
+        int p = atomicAdd(&cnt, 1);
+        if (p < FB_CAP) {
+          sm.s[p] = v;
+          sm.id[p] = (int)j;
+        }
       }
     }
+    __syncthreads();
+    L = cnt;   // uniform: every thread reads the same count
+    __syncthreads();
+    if (L <= FB_CAP || attempt == 1) break;
+    T = row_kth_radix(sm, X, d, xq, q, c0, c1, k) * up2;
   }
-  __syncthreads();
-  const int L = cnt;
-  if (L > FB_CAP) {
+  if (L > FB_CAP) {   // more than FB_CAP points within rounding of the k-th
     if (t == 0) atomicOr(overflow, 1);
-    return;
-  }
-  block_select<256, FB_CAP>(sm, L, k, tau, d, [&](int i, const float** pa, const float** pb) {
-    *pa = xq;
-    *pb = X + (int64_t)sm.id[i] * d;
-  });
-  for (int i = t; i < L; i += 256) {
-    if (sm.pos[i] >= 0) {
-      nbr[q * k + sm.pos[i]] = sm.id[i];
-      dist[q * k + sm.pos[i]] = __builtin_sqrtf(sm.s[i]);
+  } else {
+    block_select<256, FB_CAP>(sm, L, k, tau, d, [&](int i, const float** pa, const float** pb) {
+      *pa = xq;
+      *pb = X + (int64_t)sm.id[i] * d;
+    });
+    for (int i = t; i < L; i += 256) {
+      if (sm.pos[i] >= 0) {
+        nbr[q * k + sm.pos[i]] = sm.id[i];
+        dist[q * k + sm.pos[i]] = __builtin_sqrtf(sm.s[i]);
+      }
     }
+    if (t == 0) atomicAdd(&counters[1], 1ull);
   }
-  if (t == 0) atomicAdd(&counters[1], 1ull);
+  __syncthreads();   // the next row resets the count and reuses the LDS lists
+  }
 }
 
 // --------------------------------------------------------------- host side
@@ -1293,7 +1354,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   ra.ubound = (p.piped || p.hd) ? ub : nullptr;
   ra.order = spatial ? perm : nullptr;
   ra.nbr = nbr; ra.dist = dist; ra.kth_s = kth; ra.bad_flag = badf; ra.counters = ctr;
-  FAMST_TRY(launch("rerank", rerank_kernel, dim3((unsigned)n), dim3(64), 0, s, ra));
+  FAMST_TRY(launch("rerank", rerank_kernel, dim3(stride_grid(n)), dim3(64), 0, s, ra));
 
   unsigned long long hc[4] = {0, 0, 0, 0};
   int64_t nbad = 0;
@@ -1309,8 +1370,8 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
     hc[0] = (unsigned long long)nbad;
   }
   if (exact && hc[0] > 0) {
-    FAMST_TRY(launch("exact_row", exact_row_kernel, dim3((unsigned)hc[0]), dim3(256), 0, s, X, d,
-                     offs_d, B, k, bad, kth, nbr, dist, ctr, ovf));
+    FAMST_TRY(launch("exact_row", exact_row_kernel, dim3(stride_grid((int64_t)hc[0])), dim3(256), 0, s, X, d,
+                     offs_d, B, k, bad, kth, nbr, dist, ctr, ovf, (int64_t)hc[0]));
     int hov = 0;
     FAMST_HIP(hipMemcpyAsync(hc, ctr, 32, hipMemcpyDeviceToHost, s));
     FAMST_HIP(hipMemcpyAsync(&hov, ovf, 4, hipMemcpyDeviceToHost, s));

@@ -233,3 +233,56 @@ def test_famst_k64_end_to_end():
     W = float(out.W[0].item())
     assert abs(W - ref.W) <= 1e-5 * ref.W
     assert out.deltas == ref.deltas and len(out.tu) == len(X) - 1
+
+
+def _cancellation_inputs(kind, n, d, seed):
+    """Inputs where |x|^2 + |y|^2 - 2 x.y cancels: a large common offset with
+    sub-unit spread, near-duplicate clusters far from the origin (with exact
+    copies), and half of the rows offset far from the other half."""
+    rng = np.random.default_rng(seed)
+    if kind == "offset":
+        X = 1000.0 + 0.01 * rng.standard_normal((n, d))
+    elif kind == "far_clusters":
+        c = rng.standard_normal((20, d))
+        c *= 100.0 / np.linalg.norm(c, axis=1, keepdims=True)
+        X = c[rng.integers(0, 20, n)] + 1e-3 * rng.standard_normal((n, d))
+        X[n // 2:n // 2 + 40] = X[:40]           # exact copies
+    else:
+        X = rng.standard_normal((n, d))
+        X[n // 2:] = 500.0 + 0.05 * rng.standard_normal((n - n // 2, d))
+    return np.ascontiguousarray(X, dtype=np.float32)
+
+
+@pytest.mark.parametrize("kind", ["offset", "far_clusters", "mixed"])
+@pytest.mark.parametrize("prec,d,k", [("fp32", 32, 10), ("fp32", 100, 10), ("bf16", 32, 10), ("bf16", 200, 10),
+                                      ("fp8", 64, 10), ("bf16", 48, 30), ("fp32", 150, 30), ("fp8", 130, 30)])
+def test_exact_mode_certificate_under_cancellation(kind, prec, d, k):
+    # the exactness certificate rests on an error bound for the screened
+    # expansion; where it cancels catastrophically, rows must fall back to
+    # exact recomputation rather than be certified with wrong lists
+    n = 2500
+    print(f"case {kind} {prec} n={n} d={d} k={k}", flush=True)
+    X = _cancellation_inputs(kind, n, d, seed=d + k)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True)
+    print("stats", st, flush=True)
+    _check_exact(X, k, nbr, dist)
+    if kind == "offset":
+        # the screening error dwarfs every distance: nothing can be certified
+        assert st["uncertified"] == n and st["recomputed"] == n
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_exact_mode_certificate_spatial_order_offset(prec):
+    # one cloud large enough for the spatially ordered scan, half of it with
+    # a large offset; sampled rows against the oracle over all points
+    n, d, k = 40_000, 32, 10
+    print(f"case mixed-offset spatial {prec} n={n}", flush=True)
+    X = _cancellation_inputs("mixed", n, d, seed=5)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True)
+    print("stats", st, flush=True)
+    rows = np.sort(np.random.default_rng(1).choice(n, 160, replace=False))
+    ref_n, ref_s = oracle.knn_exact(X, k, rows=rows, block=32)
+    for i, r in enumerate(rows):
+        assert set(nbr[r].tolist()) == set(ref_n[i].tolist()), r
+    np.testing.assert_allclose(np.sort(dist[rows], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5, atol=1e-6)
+    assert st["uncertified"] >= n // 2 - 100

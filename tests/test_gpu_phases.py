@@ -47,11 +47,23 @@ def test_graph_and_components_bit_exact(k, n):
         assert np.array_equal(members[comp_ptr[c]:comp_ptr[c + 1]], m)
 
 
-def _pair_sets(u, v, a, b):
-    out = {}
-    for uu, vv, aa, bb in zip(u.tolist(), v.tolist(), a.tolist(), b.tolist()):
+def _pair_lists(u, v, a, b, w=None):
+    """Per component pair, its entries in stored order: (u, v) and, with w,
+    the weights (Alg. 3 keeps each pair's samples in ascending (s, q)
+    order, so the lists are compared entry by entry)."""
+    out, ws = {}, {}
+    w = np.zeros(len(u)) if w is None else w
+    for uu, vv, aa, bb, ww in zip(u.tolist(), v.tolist(), a.tolist(), b.tolist(), w.tolist()):
         out.setdefault((aa, bb), []).append((uu, vv))
-    return {key: sorted(val) for key, val in out.items()}
+        ws.setdefault((aa, bb), []).append(ww)
+    return out, ws
+
+
+def _check_pairs(got, ref, keys=None):
+    (gp, gw), (rp, rw) = got, ref
+    for key in (rp if keys is None else keys):
+        assert gp[key] == rp[key], key
+        np.testing.assert_allclose(gw[key], rw[key], rtol=1e-5)
 
 
 @pytest.mark.parametrize("k,lam,seed,n", [(2, 5, 0, 2500), (1, 3, 7, 600), (10, 5, 0, 2500),
@@ -69,10 +81,11 @@ def test_lambda_edges_match_oracle(k, lam, seed, n):
     Eref = oracle.random_edges(X, comps_ref, lam, seed)
     u, v, w, a, b = _edges_np(E)
     assert len(u) == len(Eref) == lam * t * (t - 1) // 2
-    # entry order: pairs in (a, b) order, lambda entries each
+    # entry order: pairs in (a, b) order, lambda entries each in ascending
+    # (s, sample) order; every entry with its own weight
     assert np.array_equal(a, Eref.a) and np.array_equal(b, Eref.b)
-    assert _pair_sets(u, v, a, b) == _pair_sets(Eref.u, Eref.v, Eref.a, Eref.b)
-    np.testing.assert_allclose(np.sort(w), np.sort(np.sqrt(Eref.s)), rtol=1e-5)
+    assert np.array_equal(u, Eref.u) and np.array_equal(v, Eref.v)
+    np.testing.assert_allclose(w, np.sqrt(Eref.s), rtol=1e-5)
 
 
 def test_lambda_edges_batched_use_cloud_counter():
@@ -83,7 +96,7 @@ def test_lambda_edges_batched_use_cloud_counter():
     u, v, w, a, b = _edges_np(E)
     comp = G.comp.cpu().numpy()
     base = 0
-    got = _pair_sets(u, v, a, b)
+    got = _pair_lists(u, v, a, b, w)
     for cb in range(3):
         Xb = X[offs[cb]:offs[cb + 1]]
         nb_local = nbr[offs[cb]:offs[cb + 1]] - offs[cb]
@@ -91,9 +104,8 @@ def test_lambda_edges_batched_use_cloud_counter():
         assert G.n_comp[cb] == len(comps_ref)
         np.testing.assert_array_equal(comp[offs[cb]:offs[cb + 1]], comp_ref + base)
         Eref = oracle.random_edges(Xb, comps_ref, lam, seed, cloud=cb)
-        ref = _pair_sets(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base, Eref.b + base)
-        for key, val in ref.items():
-            assert got[key] == val
+        _check_pairs(got, _pair_lists(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base, Eref.b + base,
+                                      np.sqrt(Eref.s)))
         base += len(comps_ref)
 
 
@@ -109,7 +121,7 @@ def test_connect_many_clouds(n_clouds):
     G, E = _connect(X, nbr, lam, seed, offs=offs)
     comp = G.comp.cpu().numpy()
     u, v, w, a, b = _edges_np(E)
-    got = _pair_sets(u, v, a, b)
+    got = _pair_lists(u, v, a, b, w)
     base, P = 0, 0
     for cb in range(n_clouds):
         sl = slice(offs[cb], offs[cb + 1])
@@ -119,9 +131,8 @@ def test_connect_many_clouds(n_clouds):
         np.testing.assert_array_equal(comp[sl], comp_ref + base)
         if cb % 37 == 0:
             Eref = oracle.random_edges(X[sl], comps_ref, lam, seed, cloud=cb)
-            ref = _pair_sets(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base, Eref.b + base)
-            for key, val in ref.items():
-                assert got[key] == val
+            _check_pairs(got, _pair_lists(Eref.u + offs[cb], Eref.v + offs[cb], Eref.a + base,
+                                          Eref.b + base, np.sqrt(Eref.s)))
         base += t
         P += t * (t - 1) // 2
     assert len(u) == lam * P
@@ -195,10 +206,7 @@ def test_many_components_k1_sampled_pairs_and_edges():
     ai = rng.integers(0, t - 1, size=300)
     pairs = sorted({(int(x), int(rng.integers(x + 1, t))) for x in ai})
     Eref = oracle.random_edges(X, comps_ref, lam, seed, pairs=pairs)
-    got = _pair_sets(u, v, a, b)
-    ref = _pair_sets(Eref.u, Eref.v, Eref.a, Eref.b)
-    for key, val in ref.items():
-        assert got[key] == val, key
+    _check_pairs(_pair_lists(u, v, a, b, w), _pair_lists(Eref.u, Eref.v, Eref.a, Eref.b, np.sqrt(Eref.s)))
     # refinement: a sample of edges followed through the rounds the GPU ran
     pick = np.sort(rng.choice(len(u), size=3000, replace=False))
     Es = _edges_to_oracle(u[pick], v[pick], w[pick], a[pick], b[pick])

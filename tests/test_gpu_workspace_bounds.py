@@ -81,3 +81,70 @@ def test_pipeline_entry_points_stay_in_workspace(guarded):
     assert {"famst_knn_graph", "famst_connect", "famst_refine", "famst_mst", "famst_mst_backward",
             "famst_mst_dense_fused"} <= names
     _check(guarded)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_undersized_or_misaligned_workspace_is_rejected():
+    # EWORKSPACE before any work is queued: outputs keep their contents
+    lib = L.load()
+    X = torch.from_numpy(datagen.blobs(n=600, d=16, seed=2)).to(DEV)
+    n, d, k = 600, 16, 5
+    nbr = torch.full((n, k), -7, dtype=torch.int32, device=DEV)
+    dist = torch.full((n, k), -7.0, device=DEV)
+    sz = ctypes.c_size_t(0)
+    s = A._stream()
+    assert lib.famst_knn_graph(_p(X), n, d, None, 1, k, L.FAMST_FP32, 0, _p(nbr), _p(dist), None, None,
+                               ctypes.byref(sz), s) == L.FAMST_OK
+    need = sz.value
+    ws = torch.empty(need + 512, dtype=torch.uint8, device=DEV)
+    small = ctypes.c_size_t(need - 256)
+    assert lib.famst_knn_graph(_p(X), n, d, None, 1, k, L.FAMST_FP32, 0, _p(nbr), _p(dist), None, _p(ws),
+                               ctypes.byref(small), s) == L.FAMST_EWORKSPACE
+    full = ctypes.c_size_t(need + 256)
+    off = ctypes.c_void_p(ws.data_ptr() + 16)   # not 256-byte aligned
+    assert lib.famst_knn_graph(_p(X), n, d, None, 1, k, L.FAMST_FP32, 0, _p(nbr), _p(dist), None, off,
+                               ctypes.byref(full), s) == L.FAMST_EWORKSPACE
+    torch.cuda.synchronize()
+    assert bool(torch.all(nbr == -7)) and bool(torch.all(dist == -7.0))
+
+
+def test_connect_capacity_reports_required_size_and_keeps_labels():
+    # e_cap below lambda * t (t - 1) / 2: ECAPACITY, the required count in
+    # n_edges, graph and components complete, E untouched
+    lib = L.load()
+    X = datagen.blobs(n=3000, d=32, n_clusters=10, seed=0)
+    Xd = torch.from_numpy(X).to(DEV)
+    k, lam = 2, 4
+    nbr, _ = F.knn_graph(Xd, k, precision="fp32", exact=True)
+    G_ref, E_ref = F.connect(Xd, nbr, lam, 3)
+    t = G_ref.n_comp[0]
+    need_edges = lam * t * (t - 1) // 2
+    assert t > 2 and len(E_ref) == need_edges
+    n = len(X)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=DEV)
+    col = torch.empty(2 * n * k, dtype=torch.int32, device=DEV)
+    comp = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    members = torch.empty(n, dtype=torch.int32, device=DEV)
+    comp_ptr = torch.empty(n + 1, dtype=torch.int64, device=DEV)
+    cap = need_edges - 1
+    eu = torch.full((cap,), -9, dtype=torch.int32, device=DEV)
+    ev, ea, eb = (torch.full((cap,), -9, dtype=torch.int32, device=DEV) for _ in range(3))
+    ew = torch.full((cap,), -9.0, device=DEV)
+    n_col, n_edges = ctypes.c_int64(0), ctypes.c_int64(0)
+    n_comp = (ctypes.c_int32 * 1)()
+    args = [_p(Xd), n, 32, None, 1, _p(nbr), k, lam, ctypes.c_uint64(3), _p(row_ptr), _p(col), ctypes.byref(n_col),
+            _p(comp), _p(members), _p(comp_ptr), n_comp, _p(eu), _p(ev), _p(ew), _p(ea), _p(eb), cap,
+            ctypes.byref(n_edges)]
+    sz = ctypes.c_size_t(0)
+    assert lib.famst_connect(*args, None, ctypes.byref(sz), A._stream()) == L.FAMST_OK
+    ws = torch.empty(max(sz.value, 256), dtype=torch.uint8, device=DEV)
+    code = lib.famst_connect(*args, _p(ws), ctypes.byref(sz), A._stream())
+    torch.cuda.synchronize()
+    assert code == L.FAMST_ECAPACITY
+    assert n_edges.value == need_edges and n_comp[0] == t
+    assert torch.equal(comp, G_ref.comp) and n_col.value == G_ref.col.numel()
+    assert torch.equal(row_ptr, G_ref.row_ptr) and torch.equal(col[:n_col.value], G_ref.col)
+    assert bool(torch.all(eu == -9)) and bool(torch.all(ew == -9.0))
