@@ -57,6 +57,18 @@ MEASURED_TRAFFIC = {
 }
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_weights.json")
+
+
+def golden(name):
+    """The oracle's stored FAMST result for a workload (written by
+    tests/golden/make_oracle_weights.py), or None."""
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as f:
+        return json.load(f).get(name)
+
+
 def measured_traffic(kernel, workload):
     """HBM GB per launch measured by the counters, or None if the kernel's
     sources changed since (or no measurement exists)."""
@@ -174,6 +186,15 @@ def bench_clouds(args, F, torch):
     W_exact = last["exact"][3].double().cpu().numpy()
     W_k16 = last["k16"][0].W.double().cpu().numpy()
     rel = (W_k16 - W_exact) / W_exact
+    weight = None
+    g = golden("clouds-256-d64")
+    if g is not None and g["n"] == n:
+        # against the oracle: its float64 Prim per cloud (exact mode) and its
+        # FAMST per cloud (k = 16 mode, bf16 screening here)
+        ge, gf = np.array(g["W_exact"]), np.array(g["W"])
+        weight = {"exact_rel_err_vs_oracle_prim_max": float(np.max(np.abs(W_exact - ge) / ge)),
+                  "k16_bf16_rel_err_vs_oracle_famst_max": float(np.max(np.abs(W_k16 - gf) / gf)),
+                  "oracle_famst_rel_err_vs_exact_mean": float(np.mean((gf - ge) / ge))}
     ex = res["exact"]
     val = n / (ex["ms_per_step"] * 1e-3)
     gbs = prim_bytes / (ex["kernel_avg_ms"] * 1e-3) / 1e9 if ex["kernel_avg_ms"] else None
@@ -195,8 +216,77 @@ def bench_clouds(args, F, torch):
                                                      "min": float(rel.min()), "clouds": int(len(rel))},
                      "points_per_s": round(n / (res["k16"]["ms_per_step"] * 1e-3), 1),
                      "phases_ms_per_step": res["k16"]["phases"]},
+        "weight": weight,
         "cpu_baseline": None,
     }
+
+
+def _subsample(name):
+    import datagen
+    if name == "vmf-4m-d96":
+        return "vmf-4m-d96-sub100k", datagen.subsample(4_000_000, 100_000, seed=1)
+    if name == "lowrank-500k-d960":
+        return "lowrank-500k-d960-sub50k", datagen.subsample(500_000, 50_000, seed=1)
+    return None, None
+
+
+def bench_workload(args, F, torch, name, precs, pk):
+    """One single-cloud workload at full size: time per step, points/s and the
+    distance kernel's roofline per precision; the weight error of each
+    precision against the oracle's FAMST on the stored subsample."""
+    import datagen
+    gen_name, kw, k, lam = WORKLOADS[name]
+    t0 = time.perf_counter()
+    X = getattr(datagen, gen_name)(seed=0, **kw)
+    n, d = X.shape
+    log(f"generated {name}: n={n} d={d} in {time.perf_counter() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to("cuda:0")
+    flops = 2.0 * n * n * d
+    block = {"n": n, "d": d, "k": k, "lambda": lam}
+    for prec, steps, warmup in precs:
+        exact = prec == "fp32"
+        ms, out, ph = time_path(F, torch, Xd, k, lam, args.seed, args.rounds, prec, exact, steps, warmup, True)
+        dt = ph.get("dist_topk", {})
+        avg = dt["total_ms"] / dt["launches"] if dt.get("launches") else None
+        tf = flops / (avg * 1e-3) / 1e12 if avg else None
+        block[prec] = {"mode": "exact" if exact else "screening + fp32 re-rank", "steps": steps,
+                       "ms_per_step": round(ms, 3), "points_per_s": round(n / (ms * 1e-3), 1),
+                       "W": float(out.W[0].item()), "components": out.graph.n_comp[0],
+                       "dist_topk_avg_ms": round(avg, 3) if avg else None,
+                       "dist_topk_tflops": round(tf, 2) if tf else None,
+                       "frac_of_peak": round(tf / PEAK_TFLOPS[prec], 4) if tf else None,
+                       "frac_of_measured": round(tf / pk[f"mfma_{prec}_tflops"], 4) if tf and pk else None,
+                       "traffic_GB_per_launch": measured_traffic("dist_topk", name) if prec == "bf16" else None}
+        log(f"{name} {prec}: {ms:.1f} ms/step")
+    del Xd
+    sub, idx = _subsample(name)
+    g = golden(sub) if sub else None
+    if g is not None:
+        Xs = torch.from_numpy(np.ascontiguousarray(X[idx])).to("cuda:0")
+        err = {}
+        for prec, _, _ in precs:
+            out = F.famst(Xs, k, lam, seed=g["seed"], max_rounds=g["max_rounds"], precision=prec,
+                          exact=prec == "fp32")
+            err[f"rel_err_{prec}_vs_oracle"] = (float(out.W[0].item()) - g["W"]) / g["W"]
+        block["weight_on_subsample"] = dict(subsample=sub, n=g["n"], W_oracle_famst=g["W"], **err)
+        del Xs
+    torch.cuda.empty_cache()
+    return block
+
+
+def bench_more_workloads(args, F, torch, pk):
+    """The other measured workloads, timed with fewer steps (one JSON line
+    holds them all): 500K x 960 in bf16, fp8 and fp32; 4M x 96 in bf16 and
+    fp8 (the fp32 path takes about 24 s per step there and is left out);
+    the 256 clouds in their exact and k = 16 modes."""
+    out = {}
+    out["lowrank-500k-d960"] = bench_workload(args, F, torch, "lowrank-500k-d960",
+                                              [("bf16", 2, 1), ("fp8", 2, 1), ("fp32", 1, 0)], pk)
+    out["vmf-4m-d96"] = bench_workload(args, F, torch, "vmf-4m-d96", [("bf16", 2, 1), ("fp8", 1, 1)], pk)
+    c = bench_clouds(args, F, torch)
+    out["clouds-256-d64"] = {k2: c[k2] for k2 in ("value", "unit", "ms_per_step", "config", "roofline",
+                                                  "k16_path", "weight")}
+    return out
 
 
 def calib_copy(torch):
@@ -282,6 +372,8 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured MFMA / HBM ceilings")
     ap.add_argument("--sweep", choices=["kl", "n"], default=None,
                     help="parameter sweep on blobs instead of the timed workload (one JSON line)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the default workload (not 500K x 960, 4M x 96 and the clouds)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a plain device copy of X (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -376,10 +468,16 @@ def main():
     for name, b in gbytes.items():
         ph = phases_b.get(name)
         if ph and ph["total_ms"] > 0:
-            per_launch_ms = ph["total_ms"] / args.steps
+            per_launch_ms = ph["total_ms"] / ph["launches"]
             gbs = b / (per_launch_ms * 1e-3) / 1e9
-            bw[name] = {"algorithmic_GB": round(b / 1e9, 3), "ms_per_step": round(per_launch_ms, 3),
-                        "GB_per_s": round(gbs, 1), "frac_of_hbm": round(gbs / HBM_GBS, 4)}
+            # HBM figures only from counter bytes: gathered rows that hit in L2
+            # are in the algorithmic bytes but never reach HBM
+            hbm = measured_traffic(name, args.workload)
+            bw[name] = {"algorithmic_GB": round(b / 1e9, 3), "ms_per_launch": round(per_launch_ms, 3),
+                        "algorithmic_GB_per_s": round(gbs, 1),
+                        "hbm_GB": hbm,
+                        "hbm_GB_per_s": round(hbm / (per_launch_ms * 1e-3), 1) if hbm else None,
+                        "frac_of_hbm": round(hbm / (per_launch_ms * 1e-3) / HBM_GBS, 4) if hbm else None}
 
     # sampled exact-kNN parity at full size + the CPU oracle baseline
     rng = np.random.default_rng(1)
@@ -424,6 +522,15 @@ def main():
                "single_thread": {"value": round(len(rows1) / t_cpu1, 3), "cores": 1,
                                  "sample": f"the first {len(rows1)} of those rows; {t_cpu1:.1f} s"}}
 
+    g = golden(args.workload)
+    if g is not None and (g["n"], g["d"], g["k"], g["lam"]) == (n, d, k, lam) and args.seed == g["seed"]:
+        # Eq. (1)'s relative error against the oracle's FAMST on the same input
+        oracle_w = dict(oracle_w or {}, W_oracle_famst=g["W"],
+                        rel_err_bf16_vs_oracle=(Wb - g["W"]) / g["W"],
+                        rel_err_fp32_vs_oracle=(Wf - g["W"]) / g["W"] if not args.skip_fp32 else None,
+                        rel_err_fp8_vs_oracle=(W8 - g["W"]) / g["W"] if out_8 is not None else None,
+                        oracle_t=g["t"], oracle_refine_deltas=g["deltas"])
+    extra = None if args.only_headline else bench_more_workloads(args, F, torch, pk)
     res = {
         "metric": "points/s to approx MST at stated weight error, BF16/FP8+rerank vs FP32",
         "value": round(n / (ms_bf16 * 1e-3), 1),
@@ -453,8 +560,8 @@ def main():
         "cpu_baseline": cpu,
         "h2d": {"bytes": int(X.nbytes), "ms": round(h2d_s * 1e3, 3), "GB_per_s": round(X.nbytes / h2d_s / 1e9, 1),
                 "points_per_s_with_upload": round(n / (ms_bf16 * 1e-3 + h2d_s), 1)},
-        "weight": {"W_bf16": Wb, "W_fp32": Wf, "rel_err_bf16_vs_fp32": abs(Wb - Wf) / Wf,
-                   "W_fp8": W8, "rel_err_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None,
+        "weight": {"W_bf16": Wb, "W_fp32": Wf, "gpu_rel_diff_bf16_vs_fp32": abs(Wb - Wf) / Wf,
+                   "W_fp8": W8, "gpu_rel_diff_fp8_vs_fp32": abs(W8 - Wf) / Wf if out_8 is not None else None,
                    **(oracle_w or {})},
         "fp32_path": None if args.skip_fp32 else {
                       "ms_per_step": round(ms_fp32, 3), "points_per_s": round(n / (ms_fp32 * 1e-3), 1),
@@ -475,6 +582,7 @@ def main():
                      "frac_of_measured_fp8": round(flops / (avg_8 * 1e-3) / 1e12 / pk["mfma_fp8_tflops"], 4)
                      if nl8 and pk else None},
         "parity": parity,
+        "workloads": extra,
     }
     if args.calib_copy:
         calib_copy(torch)

@@ -547,9 +547,11 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
   return (b & 0x80u) ? -mag : mag;
 }
 
-// One wave per row: per-row scale a = amax / 448 (1 for an all-zero row),
-// e4m3 codes of x / a, the norm of the dequantised row and the norm of its
-// error; gstat as in prep_kernel.
+// One wave per row: per-row scale a = the power of two at or above
+// amax / 448 (1 for an all-zero row; at least 2^-126, so that its exponent
+// byte is its E8M0 encoding and the matrix cores can apply it), e4m3 codes
+// of x / a (every |x / a| <= 448), the norm of the dequantised row and the
+// norm of its error; gstat as in prep_kernel.
 __global__ __launch_bounds__(256) void prep_fp8_kernel(const float* __restrict__ X, int64_t n, int d,
                                                        int DP, uint8_t* __restrict__ Xq,
                                                        float* __restrict__ scl, float* __restrict__ nq,
@@ -568,7 +570,13 @@ __global__ __launch_bounds__(256) void prep_fp8_kernel(const float* __restrict__
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
-    const float a = amax > 0.f ? amax / 448.f : 1.f;
+    float a = 1.f;
+    if (amax > 0.f) {
+      int e;
+      const float m = frexpf(amax / 448.f, &e);   // amax / 448 = m 2^e, m in [0.5, 1)
+      a = ldexpf(1.f, m == 0.5f ? e - 1 : e);
+      a = fmaxf(a, 1.17549435e-38f);              // 2^-126
+    }
     float acc = 0.f, eacc = 0.f;
     for (int t = lane; t < DP; t += 64) {
       float v = t < d ? x[t] : 0.f;

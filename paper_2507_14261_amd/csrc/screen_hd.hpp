@@ -50,7 +50,9 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
     float tau, float* __restrict__ ubound, const float* __restrict__ scl, const int* __restrict__ perm) {
   constexpr int NW = HdShape<SH>::NW, QB = HdShape<SH>::QB, BN = HdShape<SH>::BN, KC = 32, QW = 16 * QB,
                 JB = BN / 16, QBLK = hd_qblk<SH>();
-  constexpr bool F8 = PREC == FAMST_FP8_E4M3;   // per-row scales: s = |y|^2 - 2 a_x a_y codes.codes
+  // float8: per-row power-of-two scales applied by the matrix cores (E8M0
+  // block scales), so the products come out as a_x a_y codes.codes
+  constexpr bool F8 = PREC == FAMST_FP8_E4M3;
   static_assert(!F8 || (HdShape<SH>::KSB == 128 && HdShape<SH>::SC == 8 && BN / 64 < NW),
                 "float8: one 128-dim K-step per stage, scales staged by the second half of the waves");
   static_assert(BN / 64 <= NW && (NW & (BN / 64 - 1)) == 0, "norm loads: one wave per 64 tile rows");
@@ -84,12 +86,12 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
     nql = ok ? nq[q] : 0.f;
     band.consts(nql, ok ? qerr[q] : 0.f, bcl0, bcl1);
   }
-  float aq[QB];   // float8 scales of the lane's queries (1 otherwise)
+  int eq[QB];   // E8M0 exponents of the float8 scales of the lane's queries (B operand rows)
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int q = wq0 + qb * 16 + i16;
     U[qb] = q < bd.q1 ? F_INF : -F_INF;
-    aq[qb] = (F8 && q < bd.q1) ? scl[q] : 1.f;
+    eq[qb] = (F8 && q < bd.q1) ? (int)((__float_as_uint(scl[q]) >> 23) & 0xFFu) : 127;
   }
   LS ls;
   LJ lj;
@@ -145,11 +147,11 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
                                        (lptr_t)(stage + SQ + SR + nw * 256), 4, 0, 0);
   };
 
+  // The accumulators of a tile start at -|y|^2 / 2 of their rows, so they
+  // end at -s'/2 with s' = |y|^2 - 2 x.y the screened value less |x|^2
+  // (scaling by -2 is exact): the filter compares them with -U/2 and needs
+  // no arithmetic per element.
   f32x4 acc[QB][JB];
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
 #pragma unroll
   for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
@@ -160,6 +162,16 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
     issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
     const char* stage = smem + cs * STG;
+    if (ck == 0) {
+      const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(tn + jb * 16 + 4 * g);
+        const f32x4 h = f32x4{-0.5f * v[0], -0.5f * v[1], -0.5f * v[2], -0.5f * v[3]};
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) acc[qb][jb] = h;
+      }
+    }
     if constexpr (F8) {
       // one K-step of 128 float8 dimensions: lane (g, i16) holds 32 bytes,
       // chunks 2g and 2g + 1 of its row
@@ -171,16 +183,19 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
         const i32x4 b1 = *reinterpret_cast<const i32x4*>(stage + r * KSB + (((2 * g + 1) ^ swz(r)) << 4));
         bq[qb] = i32x8{b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
       }
+      const float* tsc = reinterpret_cast<const float*>(stage + SQ + SR + BN * 4);
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) {
         const int r = jb * 16 + i16;
         const i32x4 a0 = *reinterpret_cast<const i32x4*>(stage + SQ + r * KSB + (((2 * g) ^ swz(r)) << 4));
         const i32x4 a1 = *reinterpret_cast<const i32x4*>(stage + SQ + r * KSB + (((2 * g + 1) ^ swz(r)) << 4));
         const i32x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        // lane (g, i16) holds K-block g of row r: the block scale is row r's
+        const int ea = (int)((__float_as_uint(tsc[r]) >> 23) & 0xFFu);
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb)
           acc[qb][jb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, bq[qb], acc[qb][jb], 0, 0, 0,
-                                                                         127, 0, 127);
+                                                                         ea, 0, eq[qb]);
       }
     }
     // query fragments of this wave (B) and row fragments (A), KX K-steps
@@ -217,41 +232,22 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
       // tile complete: screened value |y|^2 - 2 x.y, filter and insertion in
       // groups of 32 rows (lane holds rows t0h + jj*16 + 4g + r)
       const int t0 = bd.c0 + ct * BN;
-      const float* tn = reinterpret_cast<const float*>(stage + SQ + SR);
 #pragma unroll
       for (int h = 0; h < JB / 2; ++h) {
-        float nqj[2][4], cj[2][4];   // row norms and -2 (times the float8 row scale)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const f32x4 v = *reinterpret_cast<const f32x4*>(tn + (2 * h + jj) * 16 + 4 * g);
-          f32x4 c = f32x4{1.f, 1.f, 1.f, 1.f};
-          if constexpr (F8) c = *reinterpret_cast<const f32x4*>(tn + BN + (2 * h + jj) * 16 + 4 * g);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            nqj[jj][r] = v[r];
-            cj[jj][r] = -2.f * c[r];
-          }
-        }
-        auto sv = [&](int qb, int e) {
-          const float c = F8 ? cj[e >> 2][e & 3] * aq[qb] : -2.f;
-          return __builtin_fmaf(c, acc[qb][2 * h + (e >> 2)][e & 3], nqj[e >> 2][e & 3]);
-        };
+        auto sv = [&](int qb, int e) { return -2.f * acc[qb][2 * h + (e >> 2)][e & 3]; };
         unsigned qbmask = 0;
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-          float m = F_INF;
+          // sv <= U  <=>  acc >= -U / 2 (exact scaling)
+          float m = acc[qb][2 * h][0];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) m = fminf(m, sv(qb, e));
-          qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
+          for (int e = 1; e < 8; ++e) m = fmaxf(m, acc[qb][2 * h + (e >> 2)][e & 3]);
+          qbmask |= ballot(m >= -0.5f * U[qb]) ? (1u << qb) : 0u;
         }
         if (qbmask)
           insert_regs<QB, 8, true>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0, lane,
-                             g, i16);
+                                   g, i16);
       }
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb) acc[qb][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
       ck = 0;
       ct = ct + 1 == ntile ? 0 : ct + 1;
     }
