@@ -1115,11 +1115,13 @@ template <int PREC, int NKB>
 static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                      const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
   auto kern = dist_topk_v2_kernel<PREC, NKB>;
-  static bool attr = false;
-  if (!attr) {
+  // the kernel also holds static LDS (the list-initialisation scratch): ask
+  // for exactly the dynamic bytes this launch uses
+  static size_t attr = 0;
+  if (attr < p.lds) {
     FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr = true;
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
+    attr = p.lds;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
                 ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);

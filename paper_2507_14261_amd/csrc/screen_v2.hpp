@@ -16,6 +16,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   constexpr int STG = TILE + 256;       // tile + its 64 norms
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ __attribute__((aligned(16))) float iscratch[4][INIT_LDS_FLOATS];   // lists from the first rows
 
   const BlockDesc bd = desc[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -176,13 +177,16 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   f32x4 accA[QB][2], accB[QB][2];
   next_tile(0);
   products(smem, 0, accA);
+  // the first 32 rows of the scan fill the lists at once
+  init_lists<QB>(ls, lj, U, nql, bcl0, bcl1, band, kk, [&](int qb, int e) { return accA[qb][e >> 2][e & 3]; },
+                 bd.c0 + tstart * BN, bd.c1, wq0, lane, g, i16, iscratch[wave]);
   int tc = tstart;   // tile being computed
   for (int it = 0; it < ntile; ++it) {
     const char* tile = smem + (it & (PIPE - 1)) * STG;
     const int t0 = bd.c0 + tc * BN;
     tc = tc + 1 == ntile ? 0 : tc + 1;
     products(tile, 1, accB);
-    filter(accA, t0);
+    if (it > 0) filter(accA, t0);
     if (it + 1 < ntile) {
       next_tile(it + 1);
       products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
