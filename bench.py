@@ -307,35 +307,66 @@ def cpu_baseline(X, k, rows):
     return nbr, t1 - t0
 
 
+def sweep_precision(d):
+    """Screening precision of the n x d sweep: float32 up to 16 dimensions
+    (bf16's 8-bit mantissa cannot separate neighbours of dense low-dimensional
+    clouds), bf16 above; candidates re-ranked in float32 (approximate mode:
+    in two dimensions the expansion's rounding exceeds the nearest-neighbour
+    distances of a million points, so exact mode would recompute every row)."""
+    return "fp32" if d <= 16 else "bf16"
+
+
 def bench_sweep(args, F, torch):
-    """Parameter sweeps on synthetic blobs (one JSON line).
+    """Parameter sweeps on synthetic blobs (10 isotropic Gaussian clusters,
+    sigma 1, centres in [-10, 10]^d), one JSON line.
     kl: k in {5, 10, 15, 20} x lambda in {1, 2, 3, 4, 5, 10} on 10,000 x 32
-        points: relative weight error against the exact tree (dense Prim on
-        the complete graph), components t, refinement rounds, time per step.
-    n:  n in {32k, 64k, 128k, 256k, 512k, 1024k} x 32 at k = 10, lambda = 5:
-        time per step and the per-phase breakdown."""
+        points, data seeds 0, 1, 2: relative weight error against the exact
+        tree (dense Prim on the complete graph), components t (mean t-bar),
+        refinement rounds, time per step; the paper's error and time trends
+        against k and lambda.
+    nd: n in {32k, 64k, 128k, 256k, 512k, 1024k} x d in {2, 16, 32, 128,
+        544, 784} at k = 10, lambda = 5 (float32 screening up to 16
+        dimensions, bf16 above, float32 re-rank): time per step and per
+        phase, points/s, components; the paper's runtime against n and d.
+        Pairs whose screening exceeds --sweep-max-flops are skipped."""
     import datagen
     rows = []
     if args.sweep == "kl":
-        X = torch.from_numpy(datagen.blobs(n=10_000, d=32, seed=0)).to("cuda:0")
-        W_exact = float(F.mst(X, algo="prim")[3][0].item())
         for k in (5, 10, 15, 20):
             for lam in (1, 2, 3, 4, 5, 10):
-                ms, out, _ = time_path(F, torch, X, k, lam, args.seed, args.rounds, "fp32", True, 3, 1, False)
-                W = float(out.W[0].item())
-                rows.append({"k": k, "lambda": lam, "t": out.graph.n_comp[0], "rounds": out.rounds,
-                             "ms_per_step": round(ms, 3), "W": W, "rel_err_vs_exact": (W - W_exact) / W_exact})
+                per = []
+                for seed in (0, 1, 2):
+                    X = torch.from_numpy(datagen.blobs(n=10_000, d=32, seed=seed)).to("cuda:0")
+                    W_exact = float(F.mst(X, algo="prim")[3][0].item())
+                    ms, out, _ = time_path(F, torch, X, k, lam, args.seed, args.rounds, "fp32", True, 3, 1, False)
+                    W = float(out.W[0].item())
+                    per.append((ms, (W - W_exact) / W_exact, out.graph.n_comp[0], out.rounds))
+                rows.append({"k": k, "lambda": lam, "seeds": 3,
+                             "rel_err_vs_exact_mean": float(np.mean([p[1] for p in per])),
+                             "rel_err_vs_exact_max": float(np.max([p[1] for p in per])),
+                             "t_bar": float(np.mean([p[2] for p in per])),
+                             "rounds_mean": float(np.mean([p[3] for p in per])),
+                             "ms_per_step": round(float(np.mean([p[0] for p in per])), 3)})
                 log(f"k={k} lambda={lam}: {rows[-1]}")
-        config = {"workload": "blobs-10k-d32", "precision": "fp32 screening, exact", "W_exact_mst": W_exact}
+        config = {"workload": "blobs-10k-d32 (data seeds 0-2)", "precision": "fp32 screening, exact"}
     else:
-        for n in (32_768, 65_536, 131_072, 262_144, 524_288, 1_048_576):
-            X = torch.from_numpy(datagen.blobs(n=n, d=32, seed=0)).to("cuda:0")
-            ms, out, ph = time_path(F, torch, X, 10, 5, args.seed, args.rounds, "bf16", False, 3, 1, True)
-            rows.append({"n": n, "ms_per_step": round(ms, 3), "points_per_s": round(n / (ms * 1e-3), 1),
-                         "t": out.graph.n_comp[0], "rounds": out.rounds,
-                         "phases_ms_per_step": {kk: round(v["total_ms"] / 3, 3) for kk, v in ph.items()}})
-            log(f"n={n}: {rows[-1]['ms_per_step']} ms")
-        config = {"workload": "blobs-d32", "k": 10, "lambda": 5, "precision": "bf16 screening + fp32 re-rank"}
+        for d in (2, 16, 32, 128, 544, 784):
+            for n in (32_768, 65_536, 131_072, 262_144, 524_288, 1_048_576):
+                if 2.0 * n * n * d > args.sweep_max_flops:
+                    rows.append({"n": n, "d": d, "skipped": "screening above --sweep-max-flops"})
+                    continue
+                X = torch.from_numpy(datagen.blobs(n=n, d=d, seed=0)).to("cuda:0")
+                prec = sweep_precision(d)
+                ms, out, ph = time_path(F, torch, X, 10, 5, args.seed, args.rounds, prec, False, 2, 1, True)
+                rows.append({"n": n, "d": d, "precision": prec, "ms_per_step": round(ms, 3),
+                             "points_per_s": round(n / (ms * 1e-3), 1), "t": out.graph.n_comp[0],
+                             "rounds": out.rounds,
+                             "phases_ms_per_step": {kk: round(v["total_ms"] / 2, 3) for kk, v in ph.items()}})
+                log(f"n={n} d={d} {prec}: {rows[-1]['ms_per_step']} ms")
+                del X
+                torch.cuda.empty_cache()
+        config = {"workload": "blobs", "k": 10, "lambda": 5, "precision": "fp32 screening for d <= 16, bf16 above, "
+                  "fp32 re-rank"}
     return {"metric": f"parameter sweep ({args.sweep})", "unit": "see rows", "n_gpus": 1,
             "data": "synthetic", "config": config, "rows": rows}
 
@@ -370,8 +401,10 @@ def main():
     ap.add_argument("--skip-fp32", action="store_true", help="do not time the float32-screened path")
     ap.add_argument("--skip-fp8", action="store_true", help="do not time the float8-screened path")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured MFMA / HBM ceilings")
-    ap.add_argument("--sweep", choices=["kl", "n"], default=None,
+    ap.add_argument("--sweep", choices=["kl", "nd"], default=None,
                     help="parameter sweep on blobs instead of the timed workload (one JSON line)")
+    ap.add_argument("--sweep-max-flops", type=float, default=2.0e15,
+                    help="n x d sweep: skip pairs whose screening (2 n^2 d flops) exceeds this")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the default workload (not 500K x 960, 4M x 96 and the clouds)")
     ap.add_argument("--calib-copy", action="store_true",
