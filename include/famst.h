@@ -75,6 +75,10 @@ extern "C" {
 /* flag: rows whose screened candidate list cannot be proven to contain the
    exact k nearest neighbours are recomputed exactly */
 #define FAMST_EXACT         0x100
+/* flag: approximate neighbours by NN-Descent (Dong, Charikar and Li, WWW
+   2011; the paper's Phase 1 is PyNNDescent, Sec. 3) instead of the exact
+   screened scan; with FAMST_FP32 only (float32 direct-difference distances) */
+#define FAMST_NNDESCENT     0x200
 
 /* tree algorithms for famst_mst */
 #define FAMST_BORUVKA         0
@@ -86,6 +90,8 @@ extern "C" {
 #define FAMST_STAT_RECOMPUTED    1  /* rows recomputed exactly (FAMST_EXACT)  */
 #define FAMST_STAT_NEAR_TIES     2  /* rows whose k-boundary needed float64   */
 #define FAMST_STAT_K_CAND        3  /* candidate-list length used             */
+#define FAMST_STAT_NND_ITERS     4  /* NN-Descent iterations run               */
+#define FAMST_STAT_NND_UPDATES   5  /* list entries changed by the last one    */
 #define FAMST_NSTATS             8
 
 const char* famst_strerror(int status);
@@ -115,6 +121,16 @@ int famst_version(void);   /* major * 10000 + minor * 100 + patch */
  *   dist     out [n][k] float32 Euclidean distances
  *   stats    host int64 [FAMST_NSTATS] or NULL; if given the stream is
  *            synchronised and the counters above are stored
+ *
+ * With FAMST_NNDESCENT (precision FAMST_FP32 | FAMST_NNDESCENT) the lists
+ * are NN-Descent's instead: every point starts from the 32 points that
+ * follow it in its cloud (cyclically) and the lists are refined by local
+ * joins (up to 8 new and 8 old samples per list and as many reverse
+ * samples, proposals beating a list's 32nd entry) until fewer than 0.1 % of
+ * the entries change, at most 16 iterations; nbr[i] holds the k best found,
+ * in ascending (s, j) order, with float32 direct-difference distances.
+ * Deterministic; no certificate (the lists are approximate).  Needs
+ * k <= 32, d <= 256, n < 2^30 (FAMST_ENOTIMPL otherwise).
  * Errors: EINVAL, ENONFINITE (checked on the device; the stream is then
  * synchronised), EWORKSPACE, EHIP; ECAPACITY in exact mode when more than
  * 2048 points of a cloud lie within float32 rounding of a recomputed row's

@@ -20,6 +20,7 @@ FAMST_FP32 = 0
 FAMST_BF16 = 1
 FAMST_FP8_E4M3 = 2
 FAMST_EXACT = 0x100
+FAMST_NNDESCENT = 0x200
 
 FAMST_BORUVKA = 0
 FAMST_KRUSKAL = 1

@@ -58,22 +58,29 @@ def _workspace(fn, *args):
 
 # ------------------------------------------------------------ Phase 1
 def knn_graph(X, k: int, precision: str = "fp32", exact: bool = False, k_cand: int = 0,
-              offs=None, with_stats: bool = False):
-    """k nearest neighbours per point (Alg. 1 GetANNs).  Returns (nbr int32
-    [n, k], dist float32 [n, k]) and, with ``with_stats``, a dict."""
+              offs=None, with_stats: bool = False, algo: str = "exact"):
+    """k nearest neighbours per point (Alg. 1 GetANNs): ``algo="exact"``
+    (matrix-core screening + float32 re-rank) or ``"nndescent"``
+    (approximate, float32).  Returns (nbr int32 [n, k], dist float32 [n, k])
+    and, with ``with_stats``, a dict."""
     lib = L.load()
     X = _dev(X, torch.float32, "X")
     n, d = X.shape
     o, B = _offs(offs, n)
     nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
     dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    if algo not in ("exact", "nndescent"):
+        raise ValueError("algo must be 'exact' or 'nndescent'")
     prec = _PREC[precision] | (L.FAMST_EXACT if exact else 0)
+    if algo == "nndescent":
+        prec = L.FAMST_FP32 | L.FAMST_NNDESCENT
     st = (ctypes.c_int64 * L.FAMST_NSTATS)() if with_stats else None
     code, _ = _workspace(lib.famst_knn_graph, _ptr(X), n, d, _offs_ptr(o), B, k, prec, k_cand,
                          _ptr(nbr), _ptr(dist), st)
     L.check(code, "famst_knn_graph")
     if with_stats:
-        stats = {"uncertified": st[0], "recomputed": st[1], "near_ties": st[2], "k_cand": st[3]}
+        stats = {"uncertified": st[0], "recomputed": st[1], "near_ties": st[2], "k_cand": st[3],
+                 "nnd_iterations": st[4], "nnd_updates": st[5]}
         return nbr, dist, stats
     return nbr, dist
 
@@ -265,11 +272,12 @@ class FamstOut:
 
 def famst(X, k: int, lam: int, seed: int = 0, max_rounds: int = 10, precision: str = "fp32",
           exact: bool | None = None, algo: str = "boruvka", offs=None, keep_initial: bool = False,
-          e_cap: int | None = None, with_stats: bool = False) -> FamstOut:
-    """The whole FAMST pipeline (Alg. 1) on the device."""
+          e_cap: int | None = None, with_stats: bool = False, knn: str = "exact") -> FamstOut:
+    """The whole FAMST pipeline (Alg. 1) on the device; ``knn="nndescent"``
+    builds Phase 1 by NN-Descent."""
     if exact is None:
-        exact = precision == "fp32"
-    r = knn_graph(X, k, precision=precision, exact=exact, offs=offs, with_stats=with_stats)
+        exact = precision == "fp32" and knn == "exact"
+    r = knn_graph(X, k, precision=precision, exact=exact, offs=offs, with_stats=with_stats, algo=knn)
     nbr, dist = r[0], r[1]
     stats = r[2] if with_stats else None
     G, E = connect(X, nbr, lam, seed, offs=offs, e_cap=e_cap)

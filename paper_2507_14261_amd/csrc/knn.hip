@@ -1211,9 +1211,35 @@ static int spatial_order(int pprec, int pnkb, const void* Pq, const float* pn, i
                 reinterpret_cast<const char*>(Xq), RS, nq, qerr, scl, perm, n, Xp, nqp, qerrp, sclp);
 }
 
+// Spatial order of the n rows of X alone (for NN-Descent's initial lists):
+// nearest of the NPIV pivot rows on the 128-coordinate bf16 sketch, rows
+// stably sorted by pivot; perm[p] = the row at position p.  With ws == NULL
+// only the workspace bytes are returned (in *bytes).
+int spatial_perm(const float* X, int64_t n, int d, int* perm, void* ws, size_t* bytes, hipStream_t s) {
+  Carve cv(ws);
+  uint16_t* skx = cv.take<uint16_t>((size_t)n * 128);
+  float* sknq = cv.take<float>(n);
+  uint32_t* key = cv.take<uint32_t>(n);
+  uint32_t* key2 = cv.take<uint32_t>(n);
+  int* idx = cv.take<int>(n);
+  const size_t tmpb = sort_pairs_u32_i32_bytes(n);
+  void* tmp = cv.take<char>(tmpb);
+  if (!ws) {
+    *bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
+  FAMST_TRY(launch("sketch", sketch_kernel, pgrid, dim3(256), 0, s, X, n, d, skx, sknq));
+  FAMST_TRY(dispatch_pivots(FAMST_BF16, 4, n, s, skx, sknq, key, idx));
+  return sort_pairs_u32_i32(tmp, tmpb, key, key2, idx, perm, (size_t)n, NPIV_BITS, s);
+}
+
 }  // namespace famst
 
 using namespace famst;
+
+int famst_nndescent_run(const float* X, int64_t n, int32_t d, const int64_t* offs, int32_t B, int32_t k,
+                        int32_t* nbr, float* dist, int64_t* stats, void* ws, size_t* ws_bytes, hipStream_t s);
 
 extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
                                int32_t B, int32_t k, int32_t precision, int32_t k_cand,
@@ -1223,7 +1249,9 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (n < 2 || d < 1 || k < 1 || k > 64 || B < 1) return FAMST_EINVAL;
   const int prec = precision & 0xFF;
   const bool exact = (precision & FAMST_EXACT) != 0;
-  if ((precision & ~(0xFF | FAMST_EXACT)) != 0) return FAMST_EINVAL;
+  const bool nnd = (precision & FAMST_NNDESCENT) != 0;
+  if ((precision & ~(0xFF | FAMST_EXACT | FAMST_NNDESCENT)) != 0) return FAMST_EINVAL;
+  if (nnd && (exact || prec != FAMST_FP32)) return FAMST_EINVAL;
   if (prec != FAMST_FP32 && prec != FAMST_BF16 && prec != FAMST_FP8_E4M3) return FAMST_EINVAL;
   int64_t one[2] = {0, n};
   const int64_t* offs = offs_h ? offs_h : one;
@@ -1234,6 +1262,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
     if (nb < 2 || k > nb - 1) return FAMST_EINVAL;
   }
   if (n >= (int64_t(1) << 31)) return FAMST_EINVAL;
+  if (nnd) {
+    if (k_cand != 0 && k_cand != 32) return FAMST_EINVAL;
+    return famst_nndescent_run(X, n, d, offs, B, k, nbr, dist, stats, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  }
   KnnPlan p;
   FAMST_TRY(choose_plan(prec, d, k, k_cand, p));
   int nblk = 0;

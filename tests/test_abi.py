@@ -60,7 +60,7 @@ def test_constants_match_header():
     for name in ["FAMST_OK", "FAMST_EINVAL", "FAMST_ECAPACITY", "FAMST_EDISCONNECTED", "FAMST_EHIP",
                  "FAMST_ENOTIMPL", "FAMST_ENONFINITE", "FAMST_EWORKSPACE", "FAMST_WNOTCONVERGED",
                  "FAMST_FP32", "FAMST_BF16", "FAMST_FP8_E4M3", "FAMST_EXACT", "FAMST_BORUVKA",
-                 "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS"]:
+                 "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS", "FAMST_NNDESCENT"]:
         m = re.search(r"#define\s+" + name + r"\s+\(?(-?\w+)\)?", txt)
         assert m, name
         assert int(m.group(1), 0) == getattr(L, name), name
@@ -151,3 +151,20 @@ def test_noalloc_gradient_limits_on_the_host():
         lib.famst_mst_backward_noalloc(None, mid, 8, None, 1, None, None, None, None, ctypes.byref(need), None)
         lo, hi = (mid, hi) if need.value <= L.FAMST_NOALLOC_SCRATCH_BYTES else (lo, mid)
     assert lo >= 1_000_000
+
+
+def test_nndescent_flag_checks_on_the_host():
+    # NN-Descent runs in float32 only, approximately, for k <= 32 and d <= 256
+    L = _lib()
+    lib = L.load()
+    sz = ctypes.c_size_t(0)
+
+    def q(d, k, prec):
+        return lib.famst_knn_graph(None, 5000, d, None, 1, k, prec, 0, None, None, None, None, ctypes.byref(sz),
+                                   None)
+
+    assert q(32, 10, L.FAMST_FP32 | L.FAMST_NNDESCENT) == L.FAMST_OK and sz.value > 5000 * 32 * 8
+    assert q(32, 10, L.FAMST_BF16 | L.FAMST_NNDESCENT) == L.FAMST_EINVAL
+    assert q(32, 10, L.FAMST_FP32 | L.FAMST_NNDESCENT | L.FAMST_EXACT) == L.FAMST_EINVAL
+    assert q(32, 33, L.FAMST_FP32 | L.FAMST_NNDESCENT) == L.FAMST_ENOTIMPL
+    assert q(300, 10, L.FAMST_FP32 | L.FAMST_NNDESCENT) == L.FAMST_ENOTIMPL
