@@ -32,27 +32,31 @@ HBM_GBS = 8000.0
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "1b15179f0b0498188ba34125ab07a24a815caa2e",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
-                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 971.4, "write_GB": 0.288,
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "02e3042a00c6048a7712f75a181fe12473bb86e9",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 967.409, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
-    ("dist_topk", "lowrank-500k-d960"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "8a18d916fbc3df3c67f8555324527b19df567f00",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
-                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 2860.3, "write_GB": 0.130,
-        "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
-    ("dist_topk", "vmf-4m-d96"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "1b15179f0b0498188ba34125ab07a24a815caa2e",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "00075a104630d2bb16a1643605f86a0f2ba78c68",
-                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 11892.2, "write_GB": 1.152,
-        "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
+    ("rerank", "gamma-int-1m-d128"): {
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "57494453dc8828ef70b687de24b33488132dde44",
+                    "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 5.268, "write_GB": 0.256,
+        "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
+    ("prep", "gamma-int-1m-d128"): {
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "57494453dc8828ef70b687de24b33488132dde44",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 0.512, "write_GB": 0.272,
+        "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
+    ("mst_backward", "gamma-int-1m-d128"): {
+        "sources": {"paper_2507_14261_amd/csrc/backward.hip": "068237775349ccb723a3d343f9d1edc4135d1886",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 1.704, "write_GB": 0.512,
+        "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "5a7f4347b68eaf06acc8836f66e8896534e37b7c",
-                    "paper_2507_14261_amd/csrc/famst_common.hpp": "37db524557921bd456b00eb0179abbc533ad3ebb"},
-        "fetch_GB": 805.6, "write_GB": 0.409,
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 803.092, "write_GB": 0.409,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
 }
 
