@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp8": 5000.0}
 HBM_GBS = 8000.0
+FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two flops
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch) scaled by what the same
@@ -99,7 +100,7 @@ WORKLOADS = {
 
 PHASES = ["prep", "sketch", "pivots", "gather_rows", "dist_topk", "rerank", "exact_row", "sort", "scan",
           "graph_keys", "graph_fill", "uf_hook", "lambda_edges", "refine", "mst_keys", "edge_compact",
-          "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward"]
+          "boruvka_min", "boruvka_hook", "tree_weight", "mst_backward", "pair_matrix", "dense_prim_fused"]
 
 
 def log(*a):
@@ -182,10 +183,15 @@ def bench_clouds(args, F, torch):
             pl, pms = F.profile_read(ph)
             if pl:
                 res[name]["phases"][ph] = round(pms / args.steps, 3)
-    # exact path: every Prim step streams the rows still outside the tree, so
-    # one launch reads sum_i n_i (n_i - 1) / 2 rows of d float32 values
+    # exact path (d <= 64): the pair kernel evaluates each unordered pair once
+    # (64 differences, 64 fused multiply-adds, 15 additions: 207 flops) and
+    # stores both orders; each Prim step then reads one matrix entry per
+    # vertex outside the tree, so one Prim launch reads every pair's entry
+    # once: sum_i n_i (n_i - 1) / 2 floats
     sizes = np.diff(offs).astype(np.float64)
-    prim_bytes = float(np.sum(sizes * (sizes - 1) / 2)) * d * 4
+    pairs = float(np.sum(sizes * (sizes - 1) / 2))
+    prim_bytes = pairs * 4
+    pair_flops = pairs * 207
     # weight error of the k = 16 FAMST trees against the exact trees, per cloud
     W_exact = last["exact"][3].double().cpu().numpy()
     W_k16 = last["k16"][0].W.double().cpu().numpy()
@@ -200,6 +206,8 @@ def bench_clouds(args, F, torch):
                   "k16_bf16_rel_err_vs_oracle_famst_max": float(np.max(np.abs(W_k16 - gf) / gf)),
                   "oracle_famst_rel_err_vs_exact_mean": float(np.mean((gf - ge) / ge))}
     ex = res["exact"]
+    pm = ex["phases"].get("pair_matrix")
+    pm_ms = round(pm, 3) if pm else None
     val = n / (ex["ms_per_step"] * 1e-3)
     gbs = prim_bytes / (ex["kernel_avg_ms"] * 1e-3) / 1e9 if ex["kernel_avg_ms"] else None
     return {
@@ -208,13 +216,19 @@ def bench_clouds(args, F, torch):
         "warmup": args.warmup, "ms_per_step": round(ex["ms_per_step"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": "clouds-256-d64", "clouds": len(sizes), "n_total": int(n), "d": d,
-                   "mode": "exact tree (k = n_i - 1) + gradient, one persistent launch"},
+                   "mode": "exact tree (k = n_i - 1) + gradient: pair matrices, then one persistent Prim launch"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1) if gbs else None, "peak": HBM_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_GBS, 4) if gbs else None,
                      "traffic": measured_traffic("dense_prim_fused", "clouds-256-d64"),
                      "traffic_unit": "GB per launch", "kernel": "dense_prim_fused",
                      "avg_ms": round(ex["kernel_avg_ms"], 3) if ex["kernel_avg_ms"] else None,
-                     "algorithmic_GB": round(prim_bytes / 1e9, 3)},
+                     "algorithmic_GB": round(prim_bytes / 1e9, 3),
+                     "note": "sequential Prim steps (one matrix row each): bound by per-step latency, not by HBM"},
+        "pair_matrix": {"bound": "alu", "ms_per_launch": pm_ms,
+                        "achieved": round(pair_flops / (pm_ms * 1e-3) / 1e12, 2) if pm_ms else None,
+                        "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(pair_flops / (pm_ms * 1e-3) / 1e12 / FP32_VALU_TFLOPS, 4) if pm_ms else None,
+                        "algorithmic_TFLOP": round(pair_flops / 1e12, 4)},
         "k16_path": {"ms_per_step": round(res["k16"]["ms_per_step"], 3),
                      "weight_rel_err_vs_exact_mst": {"max": float(rel.max()), "mean": float(rel.mean()),
                                                      "min": float(rel.min()), "clouds": int(len(rel))},

@@ -270,14 +270,22 @@ int famst_mst_backward_noalloc(const float* X, int64_t n, int32_t d,
  * Exact tree weight and its gradient for a batch of clouds in one
  * persistent launch (FAMST with k = n_b - 1 is the exact minimum spanning
  * tree, Sec. 2.1 / Prim).  Blocks take clouds from a work queue, largest
- * first; each runs dense Prim on the complete graph of its cloud (distances
- * computed on the fly), the compensated tree weight W[b], and the rows of
+ * first; each runs dense Prim on the complete graph of its cloud, the
+ * compensated tree weight W[b], and the rows of
  *   G = dW_b / dX = sum over tree edges (i, j) of (x_i - x_j)/|x_i - x_j|
  * for that cloud.  Tree edges are written cloud by cloud in Prim insertion
  * order as (tu, tv) = (parent, child); each row of G sums its parent edge
  * first, then its children in ascending id, so G is deterministic.
  *   tu, tv, tw  out [n - B];  W out [B];  grad_X out [n][d] (unscaled G)
  * Every cloud must hold at most 12288 points (FAMST_ENOTIMPL otherwise).
+ * Distances: for d <= 64 a first kernel stores the squared distance of every
+ * pair of every cloud (the library's canonical float32 bits, nb^2 floats
+ * per cloud in the workspace) and Prim reads one matrix row per step; for
+ * d > 64 they are computed on the fly.  Both give the same tree.  The size
+ * query (ws == NULL) asks for all matrices at once; a workspace that holds
+ * at least the fixed part plus the largest cloud's matrix is accepted too,
+ * and the clouds then run in consecutive groups (largest first) whose
+ * matrices fit, with the same results; less is FAMST_EWORKSPACE.
  */
 int famst_mst_dense_fused(const float* X, int64_t n, int32_t d,
                           const int64_t* offs, int32_t B,

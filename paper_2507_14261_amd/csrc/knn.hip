@@ -1008,6 +1008,7 @@ __global__ __launch_bounds__(256) void exact_row_kernel(const float* __restrict_
 // --------------------------------------------------------------- host side
 struct KnnPlan {
   int prec, KC, DP, nkb, QB, qblk, esz;
+  int nw;         // waves per block of the pipelined kernel
   bool chunked;   // K-chunked kernel (any d, float8) instead of resident queries
   bool piped;     // register lists + pipelined tiles (k' = 32, up to 128 bf16 / 64 fp32 dims)
   bool hd;        // register lists, queries and rows streamed by K-steps (k' = 32, beyond 128 dims)
@@ -1017,10 +1018,18 @@ struct KnnPlan {
 // Zero rows past the end of the screening copy, its norms and scales: at
 // least the largest tile or query block a screening kernel reads whole.
 constexpr int PADR = 256;
-static_assert(HdShape<4>::BN <= PADR && HdShape<8>::BN <= PADR && hd_qblk<4>() <= PADR && hd_qblk<8>() <= PADR,
+static_assert(HdShape<4>::BN <= PADR && HdShape<8>::BN <= PADR && hd_qblk<4>() <= PADR && hd_qblk<8>() <= PADR &&
+                  V2Shape<8>::BN <= PADR,
               "padding covers every streamed tile and query block");
 
-static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
+// Eight-wave blocks of the pipelined kernel from this many rows of one cloud
+// on: they halve the rows streamed per query, which pays where the stream is
+// longest (4M x 96: 9 % faster) but not at 1M x 128 (15 % slower: the wider
+// barrier leaves a compute unit idle more often)
+static constexpr int64_t V2_WIDE_MIN = 2097152;
+
+static int choose_plan(int prec, int d, int k, int k_cand, int64_t nmax, KnnPlan& p) {
+  p.nw = 4;
   p.prec = prec;
   p.KC = k_cand ? k_cand : (k <= 24 ? 32 : 64);
   if (p.KC != 32 && p.KC != 64) return FAMST_EINVAL;
@@ -1049,7 +1058,9 @@ static int choose_plan(int prec, int d, int k, int k_cand, KnnPlan& p) {
     p.lds = (size_t)p.qblk * p.KC * 8 + (size_t)64 * p.DP * p.esz;
     if (p.KC == 32 && p.nkb <= 4) {
       p.piped = true;
-      p.lds = (size_t)PIPE * (64 * p.nkb * 64 + 256);
+      p.nw = nmax >= V2_WIDE_MIN ? 8 : 4;
+      p.qblk = 64 * p.nw;
+      p.lds = p.nw == 8 ? v2_lds_bytes<8>(p.nkb) : v2_lds_bytes<4>(p.nkb);
     }
   } else {
     const int cdim = KCH / p.esz;               // dims per K chunk
@@ -1111,10 +1122,10 @@ struct BandArgs {
   const int* perm;   // spatial order of the rows of Xq (null: identity)
 };
 
-template <int PREC, int NKB>
+template <int PREC, int NKB, int NW>
 static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                      const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
-  auto kern = dist_topk_v2_kernel<PREC, NKB>;
+  auto kern = dist_topk_v2_kernel<PREC, NKB, NW>;
   // the kernel also holds static LDS (the list-initialisation scratch): ask
   // for exactly the dynamic bytes this launch uses
   static size_t attr = 0;
@@ -1123,7 +1134,7 @@ static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds));
     attr = p.lds;
   }
-  return launch("dist_topk", kern, dim3(nblk), dim3(256), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
+  return launch("dist_topk", kern, dim3(nblk), dim3(64 * NW), p.lds, s, Xq, nq, p.nkb, desc, cj, cs,
                 ba.k, ba.qerr, ba.gstat, ba.arith_c, ba.tau, ba.ubound, ba.perm);
 }
 
@@ -1146,13 +1157,18 @@ template <int PREC>
 static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                        const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
   if (p.piped) {
+#define V2_CASE(NKB)                                                                                        \
+  case NKB:                                                                                                 \
+    return p.nw == 8 ? launch_v2<PREC, NKB, 8>(p, nblk, s, Xq, nq, desc, cj, cs, ba)                       \
+                     : launch_v2<PREC, NKB, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
     switch (p.nkb) {
-      case 1: return launch_v2<PREC, 1>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
-      case 2: return launch_v2<PREC, 2>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
-      case 3: return launch_v2<PREC, 3>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
-      case 4: return launch_v2<PREC, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+      V2_CASE(1)
+      V2_CASE(2)
+      V2_CASE(3)
+      V2_CASE(4)
       default: return FAMST_ENOTIMPL;
     }
+#undef V2_CASE
   }
 #define DT_CASE(NKB)                                                                        \
   if (p.nkb <= NKB) {                                                                       \
@@ -1266,8 +1282,10 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
     if (k_cand != 0 && k_cand != 32) return FAMST_EINVAL;
     return famst_nndescent_run(X, n, d, offs, B, k, nbr, dist, stats, ws, ws_bytes, static_cast<hipStream_t>(stream));
   }
+  int64_t nmax = 0;
+  for (int b = 0; b < B; ++b) nmax = std::max<int64_t>(nmax, offs[b + 1] - offs[b]);
   KnnPlan p;
-  FAMST_TRY(choose_plan(prec, d, k, k_cand, p));
+  FAMST_TRY(choose_plan(prec, d, k, k_cand, nmax, p));
   int nblk = 0;
   for (int b = 0; b < B; ++b) nblk += (int)cdiv(offs[b + 1] - offs[b], p.qblk);
   const int esz = p.esz;

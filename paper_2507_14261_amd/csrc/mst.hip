@@ -8,6 +8,8 @@
 
 #include <numeric>
 
+#include <type_traits>
+
 #include "famst_common.hpp"
 #include "prims.hpp"
 
@@ -278,6 +280,8 @@ __global__ __launch_bounds__(256) void tree_weight_kernel(const float* __restric
 // Keys are (w, min, max) as everywhere.
 constexpr int PRIM_MAX = 16384;   // local ids fit in 14 bits
 constexpr int PRIM_NT = 512;      // threads per cloud
+constexpr int PRIM_NT_DM = 1024;  // threads per cloud, Prim over the pair matrices
+constexpr int PRIM_RD = 8;        // matrix entries in flight per thread while the list is long
 
 __device__ __forceinline__ bool ekey_less(float w1, int a1, int b1, float w2, int a2, int b2) {
   int l1 = min(a1, b1), h1 = max(a1, b1), l2 = min(a2, b2), h2 = max(a2, b2);
@@ -320,6 +324,33 @@ __device__ __forceinline__ void quad_partials(const float* __restrict__ a, const
     }
 }
 
+// Minimum of a 64-bit key over the wave by DPP (row shifts by 1, 2, 3, then
+// 4 and 8 across banks, then the row broadcasts 15 and 31): the minimum
+// lands in lane 63.  A lane whose DPP source does not exist keeps its own
+// key (the `old` operand), which leaves the minimum unchanged; both halves
+// of a key move with the same control, so every lane always holds a whole
+// key of some lane.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ uint64_t dpp_min_step(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t olo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, BANK_MASK, false);
+  const uint32_t ohi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, BANK_MASK, false);
+  const uint64_t o = ((uint64_t)ohi << 32) | olo;
+  return o < v ? o : v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  v = dpp_min_step<0x111, 0xF, 0xF>(v);   // row_shr:1
+  v = dpp_min_step<0x112, 0xF, 0xF>(v);   // row_shr:2
+  v = dpp_min_step<0x113, 0xF, 0xF>(v);   // row_shr:3
+  v = dpp_min_step<0x114, 0xF, 0xE>(v);   // row_shr:4, banks 1-3
+  v = dpp_min_step<0x118, 0xF, 0xC>(v);   // row_shr:8, banks 2-3
+  v = dpp_min_step<0x142, 0xA, 0xF>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_min_step<0x143, 0xC, 0xF>(v);   // row_bcast:31 into rows 2 and 3
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Selection key of a candidate edge (w, p, j), w >= 0, local ids < 2^14:
 // ordered as (w, min, max); the low bit says whether j (the vertex outside
 // the tree) is the smaller endpoint.  ~0 marks a dead list entry.
@@ -349,7 +380,7 @@ __device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
   return ekey_less(w, cur, j, w0, key_p(key), j) ? prim_key(w, cur, j) : key;
 }
 
-// Dense Prim over rows c0 .. c0 + nb - 1 by PRIM_NT threads.  `keys` holds
+// Dense Prim over rows c0 .. c0 + nb - 1 by NT threads.  `keys` holds
 // one key per vertex outside the tree (its best edge to the tree); slot q
 // belongs to quad q mod NQ, whose lane 0 alone writes it, so one barrier
 // per step suffices: the per-wave minimum keys go through LDS
@@ -359,21 +390,22 @@ __device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
 // front (their order does not matter: the minimum is over unique keys).
 // emit(step, p, j, w) is called by thread 0 for each edge, in insertion
 // order.  VEC: d == 64 and rows 16-byte aligned; FAMST_PRIM_R rows per
-// quad are in flight.  CMAX >= nb / PRIM_NT.
+// quad are in flight.  CMAX >= nb / NT.  DM: squared distances from the
+// cloud's pair matrix Dc (row-major nb x nb) instead.
 constexpr int PRIM_COMPACT = 32;
 
 #ifndef FAMST_PRIM_R
 #define FAMST_PRIM_R 8
 #endif
-template <bool VEC, int CMAX, class Emit>
+template <int NT, bool VEC, int CMAX, bool DM = false, class Emit>
 __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int nb,
                            uint64_t* __restrict__ keys, uint64_t* __restrict__ wkeys,
-                           int* __restrict__ mcount, Emit emit) {
-  constexpr int NW = PRIM_NT / 64, NQ = PRIM_NT / 4, R = FAMST_PRIM_R;   // rows in flight per lane
+                           int* __restrict__ mcount, Emit emit, const float* __restrict__ Dc = nullptr) {
+  constexpr int NW = NT / 64, NQ = NT / 4, R = FAMST_PRIM_R;   // rows in flight per lane
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, c = t & 3, g = t >> 2;
   // vertex 0 starts the tree; every other vertex has the placeholder edge
   // (+inf, 0, j), replaced in the first step
-  for (int j = 1 + t; j < nb; j += PRIM_NT) keys[j - 1] = prim_key(F_INF, 0, j);
+  for (int j = 1 + t; j < nb; j += NT) keys[j - 1] = prim_key(F_INF, 0, j);
   if (t == 0) *mcount = 0;
   __syncthreads();
   int m = nb - 1;
@@ -382,7 +414,41 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
     const float* __restrict__ xc = X + (c0 + cur) * d;
     uint64_t best = PRIM_DEAD;
     int bslot = -1;
-    if constexpr (VEC) {
+    if constexpr (DM) {
+      // one thread per list slot: the squared distances to the newest
+      // vertex are row cur of the cloud's matrix (dead slots read its
+      // diagonal, so the loads need no branches); RD slots per thread are in
+      // flight at once, fewer as the list shrinks
+      const float* __restrict__ dr = Dc + (int64_t)cur * nb;
+      auto relax_slots = [&](auto rd) {
+        constexpr int RD = decltype(rd)::value;
+        for (int q0 = t; q0 < m; q0 += NT * RD) {
+          uint64_t kk[RD];
+          float sq[RD];
+#pragma unroll
+          for (int u = 0; u < RD; ++u) {
+            const int q = q0 + u * NT;
+            kk[u] = q < m ? keys[q] : PRIM_DEAD;
+            sq[u] = dr[kk[u] != PRIM_DEAD ? key_j(kk[u]) : cur];
+          }
+#pragma unroll
+          for (int u = 0; u < RD; ++u) {
+            if (kk[u] != PRIM_DEAD) {
+              const uint64_t nk = prim_relax(kk[u], sq[u], cur);
+              const int q = q0 + u * NT;
+              if (nk != kk[u]) keys[q] = nk;
+              if (nk < best) {
+                best = nk;
+                bslot = q;
+              }
+            }
+          }
+        }
+      };
+      if (m > 4 * NT) relax_slots(std::integral_constant<int, PRIM_RD>{});
+      else if (m > NT) relax_slots(std::integral_constant<int, 4>{});
+      else relax_slots(std::integral_constant<int, 1>{});
+    } else if constexpr (VEC) {
       f32x4 xa[4];
 #pragma unroll
       for (int mm = 0; mm < 4; ++mm) xa[mm] = reinterpret_cast<const f32x4*>(xc)[c + 4 * mm];
@@ -439,12 +505,7 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
         }
       }
     }
-    uint64_t wb = best;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const uint64_t other = __shfl_xor(wb, o);
-      wb = other < wb ? other : wb;
-    }
+    const uint64_t wb = wave_min_u64(best);
     uint64_t* wk = wkeys + (step & 1) * NW;
     if (lane == 0) wk[wave] = wb;
     __syncthreads();
@@ -453,7 +514,7 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
     for (int w = 1; w < NW; ++w) gb = wk[w] < gb ? wk[w] : gb;
     const int j = key_j(gb), p = key_p(gb);
     if (t == 0) emit(step, p, j, key_w(gb));
-    if (best == gb && c == 0) keys[bslot] = PRIM_DEAD;
+    if (best == gb && (DM || c == 0)) keys[bslot] = PRIM_DEAD;   // the slot's one owner
     cur = __builtin_amdgcn_readfirstlane(j);
     if (step % PRIM_COMPACT == 0 && step + 1 < nb) {
       if (t == 0) *mcount = 0;
@@ -462,7 +523,7 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
       int cnt = 0;
 #pragma unroll
       for (int i = 0; i < CMAX; ++i) {
-        const int q = t + PRIM_NT * i;
+        const int q = t + NT * i;
         e[i] = q < m ? keys[q] : PRIM_DEAD;
         cnt += e[i] != PRIM_DEAD;
       }
@@ -496,8 +557,152 @@ __global__ __launch_bounds__(PRIM_NT) void prim_kernel(const float* __restrict__
     ow[eo + step - 1] = w;
   };
   constexpr int CM = PRIM_MAX / PRIM_NT;
-  if (vec) prim_cloud<true, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
-  else prim_cloud<false, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+  if (vec) prim_cloud<PRIM_NT, true, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+  else prim_cloud<PRIM_NT, false, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+}
+
+// ------------------------------------------------ pair distance matrices
+// For d <= 64 the squared distance of every pair of a cloud is computed once,
+// in the bits of sq32_group, and stored in both orders as the row-major
+// nb x nb matrix of the cloud at dmoff[b]; Prim then reads one matrix row
+// (4 bytes per vertex outside the tree) per step instead of the rows of
+// every such vertex (4 d bytes each).  One block per 64 x 64 tile of the
+// upper triangle of tiles; thread (ty, tx) holds the 16 pairs
+// (ty + 16 i, tx + 16 j).  The 16 chunk partials of a pair are combined as
+// sq32_group's xor butterfly (over 8, 4, 2, 1), i.e. a binary tree over the
+// chunks in bit-reversed order 0, 8, 4, 12, 2, ...; padding dimensions
+// (zero in both rows) leave a partial unchanged, as in sq32_group.
+constexpr int PD_T = 64, PD_NT = 256, PD_LD = 68;   // tile edge, threads, LDS row stride (floats)
+constexpr int DMAT_MAXD = 64;
+
+// chunk partials of chunk c for the thread's 16 pairs: dimensions
+// 4 c .. 4 c + 3, fmaf in order
+__device__ __forceinline__ void pd_leaf(const float* As, const float* Bs, int ty, int tx, int c, float (&out)[16]) {
+  f32x4 xa[4], xb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    xa[i] = *reinterpret_cast<const f32x4*>(As + (ty + 16 * i) * PD_LD + 4 * c);
+    xb[i] = *reinterpret_cast<const f32x4*>(Bs + (tx + 16 * i) * PD_LD + 4 * c);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float acc = 0.f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float df = xa[i][e] - xb[j][e];
+        acc = __builtin_fmaf(df, df, acc);
+      }
+      out[4 * i + j] = acc;
+    }
+}
+
+// The 16 leaves in bit-reversed chunk order; a finished left subtree at
+// level l waits in pend[l] until its right sibling is complete (a binary
+// counter over the leaf index).
+__device__ __forceinline__ void pd_pairs(const float* As, const float* Bs, int ty, int tx, float (&sq)[16]) {
+  float pend[4][16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int c = ((k & 1) << 3) | ((k & 2) << 1) | ((k & 4) >> 1) | ((k & 8) >> 3);
+    float v[16];
+    pd_leaf(As, Bs, ty, tx, c, v);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if ((k >> l) & 1) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) v[p] = pend[l][p] + v[p];
+      } else {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) pend[l][p] = v[p];
+        break;
+      }
+    }
+    if (k == 15) {
+#pragma unroll
+      for (int p = 0; p < 16; ++p) sq[p] = v[p];
+    }
+  }
+}
+
+__global__ __launch_bounds__(PD_NT) void pair_matrix_kernel(const float* __restrict__ X, int d,
+                                                            const int64_t* __restrict__ offs,
+                                                            const int* __restrict__ clouds, int nc,
+                                                            const int64_t* __restrict__ tpre,
+                                                            const int64_t* __restrict__ dmoff,
+                                                            float* __restrict__ D) {
+  __shared__ __attribute__((aligned(16))) float As[PD_T * PD_LD], Bs[PD_T * PD_LD];
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+  const int64_t ntiles = tpre[nc];
+  for (int64_t gi = blockIdx.x; gi < ntiles; gi += gridDim.x) {
+    // cloud of the tile (tpre: prefix of the tile counts), then (ta, tb), ta <= tb
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tpre[mid] <= gi) lo = mid;
+      else hi = mid - 1;
+    }
+    const int b = clouds[lo];
+    const int64_t c0 = offs[b];
+    const int nb = (int)(offs[b + 1] - c0);
+    const int T = (nb + PD_T - 1) / PD_T;
+    const int64_t li = gi - tpre[lo];
+    // row ta of the triangle starts at S(ta) = ta T - ta (ta - 1) / 2
+    int ta = (int)((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)li)) * 0.5);
+    ta = max(0, min(ta, T - 1));
+    auto S = [&](int r) { return (int64_t)r * T - (int64_t)r * (r - 1) / 2; };
+    while (ta > 0 && S(ta) > li) --ta;
+    while (ta + 1 < T && S(ta + 1) <= li) ++ta;
+    const int tb = ta + (int)(li - S(ta));
+    const int a0 = ta * PD_T, b0 = tb * PD_T;
+    // rows of both tiles (rows past the cloud repeat its last row, dimensions
+    // past d are zero)
+    for (int e = t; e < PD_T * 16; e += PD_NT) {
+      const int r = e >> 4, cc = e & 15;
+      const int ra = min(a0 + r, nb - 1), rb = min(b0 + r, nb - 1);
+      f32x4 va, vb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int dim = 4 * cc + i;
+        va[i] = dim < d ? X[(c0 + ra) * d + dim] : 0.f;
+        vb[i] = dim < d ? X[(c0 + rb) * d + dim] : 0.f;
+      }
+      *reinterpret_cast<f32x4*>(As + r * PD_LD + 4 * cc) = va;
+      *reinterpret_cast<f32x4*>(Bs + r * PD_LD + 4 * cc) = vb;
+    }
+    __syncthreads();
+    float sq[16];
+    pd_pairs(As, Bs, ty, tx, sq);
+    // the values are complete here: the compiler would otherwise sink each
+    // pair's arithmetic into its guarded store and read every chunk first
+#pragma unroll
+    for (int p = 0; p < 16; ++p) __asm__ volatile("" : : "v"(sq[p]));
+    float* __restrict__ Dm = D + dmoff[b];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = a0 + ty + 16 * i, c = b0 + tx + 16 * j;
+        if (a < nb && c < nb) Dm[(int64_t)a * nb + c] = sq[4 * i + j];
+      }
+    __syncthreads();   // the tile rows are read; As is reused for the transpose
+    if (ta != tb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) As[(ty + 16 * i) * PD_LD + tx + 16 * j] = sq[4 * i + j];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = b0 + ty + 16 * i, a = a0 + tx + 16 * j;
+          if (a < nb && c < nb) Dm[(int64_t)c * nb + a] = As[(tx + 16 * j) * PD_LD + ty + 16 * i];
+        }
+    }
+    __syncthreads();   // the next tile overwrites As and Bs
+  }
 }
 
 // Persistent exact-tree kernel for a batch of clouds: blocks pull clouds
@@ -508,20 +713,24 @@ __global__ __launch_bounds__(PRIM_NT) void prim_kernel(const float* __restrict__
 // children in ascending order, so it is deterministic.
 constexpr int FUSED_MAX = 12288;
 
-__global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
+// MODE: 0 distances on the fly (any d), 1 on the fly with 16-byte row loads
+// (d == 64), 2 from the pair matrices.
+template <int NT, int MODE>
+__global__ __launch_bounds__(NT) void prim_fused_kernel(
     const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
-    int B, int vec, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
-    float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad) {
+    int B, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
+    float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad, const float* __restrict__ D,
+    const int64_t* __restrict__ dmoff) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(smem);              // Prim candidate list
   int* par = reinterpret_cast<int*>(keys + FUSED_MAX);            // tree parent of each vertex
   int* endp = reinterpret_cast<int*>(smem);                       // after Prim: list ends ...
   int* kid = endp + FUSED_MAX;                                    // ... and children lists
-  __shared__ uint64_t wkeys[2 * PRIM_NT / 64];
-  __shared__ float ss[PRIM_NT], ee[PRIM_NT];
+  __shared__ uint64_t wkeys[2 * NT / 64];
+  __shared__ float ss[NT], ee[NT];
   __shared__ int cloud_s, mcount;
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
-  constexpr int NG = PRIM_NT / 16;
+  constexpr int NG = NT / 16;
   while (true) {
     if (t == 0) {
       int idx = atomicAdd(queue, 1);
@@ -542,15 +751,15 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
       ov[eo + step - 1] = (int32_t)(c0 + j);
       ow[eo + step - 1] = w;
     };
-    constexpr int CM = FUSED_MAX / PRIM_NT;
-    if (vec) prim_cloud<true, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
-    else prim_cloud<false, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+    constexpr int CM = FUSED_MAX / NT;
+    prim_cloud<NT, MODE == 1, CM, MODE == 2>(X, d, c0, nb, keys, wkeys, &mcount, emit,
+                                             MODE == 2 ? D + dmoff[b] : nullptr);
     __threadfence_block();
     __syncthreads();
     // ---- tree weight, compensated, in insertion order
     {
       float sacc = 0.f, cacc = 0.f;
-      for (int i = t; i < nb - 1; i += PRIM_NT) {
+      for (int i = t; i < nb - 1; i += NT) {
         float ns, err;
         two_sum(sacc, ow[eo + i], ns, err);
         sacc = ns;
@@ -559,7 +768,7 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
       ss[t] = sacc;
       ee[t] = cacc;
       __syncthreads();
-      for (int w = PRIM_NT / 2; w >= 1; w >>= 1) {
+      for (int w = NT / 2; w >= 1; w >>= 1) {
         if (t < w) {
           float ns, err;
           two_sum(ss[t], ss[t + w], ns, err);
@@ -571,7 +780,7 @@ __global__ __launch_bounds__(PRIM_NT) void prim_fused_kernel(
       if (t == 0) W[b] = ss[0] + ee[0];
     }
     // ---- children lists by counting sort, stable in child id (one thread)
-    for (int j = t; j < nb; j += PRIM_NT) endp[j] = 0;
+    for (int j = t; j < nb; j += NT) endp[j] = 0;
     __syncthreads();
     if (t == 0) {
       for (int c = 1; c < nb; ++c) endp[par[c]] += 1;
@@ -810,6 +1019,22 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   return FAMST_OK;
 }
 
+template <int NT, int MODE>
+static int launch_fused(dim3 grid, hipStream_t s, const float* X, int d, const int64_t* offs, const int* order, int nc,
+                        int* queue, int32_t* tu, int32_t* tv, float* tw, float* W, float* grad, const float* D,
+                        const int64_t* dmoff) {
+  auto kern = prim_fused_kernel<NT, MODE>;
+  const size_t lds = (size_t)3 * FUSED_MAX * 4;
+  static bool attr = false;
+  if (!attr) {
+    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    attr = true;
+  }
+  return launch("dense_prim_fused", kern, grid, dim3(NT), lds, s, X, d, offs, order, nc, queue, tu, tv, tw, W, grad, D,
+                dmoff);
+}
+
 extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
                                      int32_t B, int32_t* tu, int32_t* tv, float* tw, float* W,
                                      float* grad_X, void* ws, size_t* ws_bytes, void* stream) {
@@ -827,37 +1052,90 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
     if (nb > FUSED_MAX) return FAMST_ENOTIMPL;
     order[b] = b;
   }
-  Carve cv(ws);
-  int64_t* offs_d = cv.take<int64_t>(B + 1);
-  int* order_d = cv.take<int>(B);
-  int* queue = cv.take<int>(1);
-  if (!ws) {
-    *ws_bytes = cv.bytes();
-    return FAMST_OK;
-  }
-  if (*ws_bytes < cv.bytes() || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
-  if (!X || !tu || !tv || !tw || !W || !grad_X) return FAMST_EINVAL;
   // largest clouds first (longest-processing-time order), ties by index
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return offs[a + 1] - offs[a] > offs[b + 1] - offs[b];
   });
+  // d <= 64: pair matrices (nb^2 floats per cloud); the size query asks for
+  // all of them at once, and a smaller workspace that still holds the
+  // largest cloud's matrix runs the clouds in consecutive groups that fit
+  const bool dm = d <= DMAT_MAXD;
+  int64_t mtot = 0, mmax = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t nb = offs[b + 1] - offs[b];
+    mtot += nb * nb;
+    mmax = std::max(mmax, nb * nb);
+  }
+  Carve cv(ws);
+  int64_t* offs_d = cv.take<int64_t>(B + 1);
+  int* order_d = cv.take<int>(B);
+  int* queue = cv.take<int>(1);
+  int64_t* dmoff_d = cv.take<int64_t>(dm ? B : 0);
+  int64_t* tpre_d = cv.take<int64_t>(dm ? 2 * B + 1 : 0);
+  const size_t fixed = cv.bytes();
+  float* D = cv.take<float>(dm ? mtot : 0);
+  if (!ws) {
+    *ws_bytes = cv.bytes();
+    return FAMST_OK;
+  }
+  const size_t need = dm ? fixed + (size_t)mmax * 4 : cv.bytes();
+  if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
+  if (!X || !tu || !tv || !tw || !W || !grad_X) return FAMST_EINVAL;
+  // groups of clouds (consecutive in the processing order) whose matrices fit
+  const int64_t cap = dm ? (int64_t)((*ws_bytes - fixed) / 4) : 0;
+  std::vector<int> gstart{0};
+  std::vector<int64_t> dmoff(dm ? B : 0), tpre;
+  if (dm) {
+    int64_t used = 0, tiles = 0;
+    tpre.push_back(0);
+    for (int i = 0; i < B; ++i) {
+      const int b = order[i];
+      const int64_t nb = offs[b + 1] - offs[b], T = (nb + PD_T - 1) / PD_T;
+      if (used + nb * nb > cap) {   // start a new group
+        gstart.push_back(i);
+        used = 0;
+        tiles = 0;
+        tpre.push_back(0);
+      }
+      dmoff[b] = used;
+      used += nb * nb;
+      tiles += T * (T + 1) / 2;
+      tpre.push_back(tiles);
+    }
+  }
+  gstart.push_back(B);
   hipStream_t s = static_cast<hipStream_t>(stream);
   FAMST_HIP(hipMemcpyAsync(offs_d, offs, sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice, s));
   FAMST_HIP(hipMemcpyAsync(order_d, order.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
-  FAMST_HIP(hipMemsetAsync(queue, 0, sizeof(int), s));
-  FAMST_HIP(hipStreamSynchronize(s));  // host order array copied before it goes out of scope
+  if (dm) {
+    FAMST_HIP(hipMemcpyAsync(dmoff_d, dmoff.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
+    FAMST_HIP(hipMemcpyAsync(tpre_d, tpre.data(), sizeof(int64_t) * tpre.size(), hipMemcpyHostToDevice, s));
+  }
+  FAMST_HIP(hipStreamSynchronize(s));  // host arrays copied before they go out of scope
   int dev = 0, ncu = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  static bool attr = false;
-  const size_t lds = (size_t)3 * FUSED_MAX * 4;
-  if (!attr) {
-    FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(prim_fused_kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr = true;
+  const int mode = dm ? 2 : ((d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) ? 1 : 0);
+  for (size_t gi = 0; gi + 1 < gstart.size(); ++gi) {
+    const int g0 = gstart[gi], nc = gstart[gi + 1] - g0;
+    if (dm) {
+      // the group's prefix of tile counts sits at tpre[g0 + gi .. g0 + gi + nc]
+      const int64_t* tp = tpre_d + g0 + gi;
+      const int64_t ntile = tpre[g0 + gi + nc];
+      FAMST_TRY(launch("pair_matrix", pair_matrix_kernel, dim3(stride_grid(ntile)), dim3(PD_NT), 0, s, X, d,
+                       offs_d, order_d + g0, nc, tp, dmoff_d, D));
+    }
+    FAMST_HIP(hipMemsetAsync(queue, 0, sizeof(int), s));
+    const dim3 grid(std::min(nc, ncu));
+    if (mode == 2)
+      FAMST_TRY((launch_fused<PRIM_NT_DM, 2>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W,
+                                             grad_X, D, dmoff_d)));
+    else if (mode == 1)
+      FAMST_TRY((launch_fused<PRIM_NT, 1>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W, grad_X,
+                                          nullptr, nullptr)));
+    else
+      FAMST_TRY((launch_fused<PRIM_NT, 0>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W, grad_X,
+                                          nullptr, nullptr)));
   }
-  const int grid = std::min(B, ncu);
-  const int vec = (d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
-  return launch("dense_prim_fused", prim_fused_kernel, dim3(grid), dim3(PRIM_NT), lds, s, X, d, offs_d,
-                order_d, B, vec, queue, tu, tv, tw, W, grad_X);
+  return FAMST_OK;
 }

@@ -4,19 +4,35 @@
 
 namespace famst {
 
-template <int PREC, int NKB>
-__global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
+// Block shape of the pipelined screening: NW waves of 64 queries share tiles
+// of 16 NW rows.  Four waves (two blocks per compute unit) suit batches of
+// small clouds; eight waves (one block per compute unit) halve the rows
+// streamed per query on one large cloud, at the price of a barrier across
+// twice as many waves.
+template <int NW>
+struct V2Shape {
+  static constexpr int NT = 64 * NW, BN = 16 * NW, GR = BN / 32;   // threads, tile rows, 32-row groups
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
+};
+template <int NW>
+constexpr size_t v2_lds_bytes(int nkb) {
+  return (size_t)PIPE * (V2Shape<NW>::BN * nkb * 64 + 4 * V2Shape<NW>::BN);
+}
+
+template <int PREC, int NKB, int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
     int kk, const float* __restrict__ qerr, const unsigned* __restrict__ gstat, float arith_c,
     float tau, float* __restrict__ ubound, const int* __restrict__ perm) {
   using S = Scr<PREC>;
-  constexpr int QB = 4, KC = 32, QW = 64, BN = 64;
-  constexpr int TILE = BN * NKB * 64;   // 64 rows x NKB 64-byte chunks
-  constexpr int STG = TILE + 256;       // tile + its 64 norms
+  constexpr int QB = 4, KC = 32, QW = 64, BN = V2Shape<NW>::BN, NT = V2Shape<NW>::NT, GR = V2Shape<NW>::GR;
+  constexpr int TILE = BN * NKB * 64;   // BN rows x NKB 64-byte chunks
+  constexpr int STG = TILE + 4 * BN;    // tile + its BN norms
+  static_assert(GR % 2 == 0, "32-row groups alternate between two accumulator sets");
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ __attribute__((aligned(16))) float iscratch[4][INIT_LDS_FLOATS];   // lists from the first rows
+  __shared__ __attribute__((aligned(16))) float iscratch[NW][INIT_LDS_FLOATS];   // lists from the first rows
 
   const BlockDesc bd = desc[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -66,10 +82,11 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   // (p mod cpr) ^ (row & smask) of row p / cpr (the XOR swizzle of
   // dist_topk_kernel), so lane l of a wave fetches the chunk that lands at
   // its slot; its byte offset from the tile's first row is the same for
-  // every tile.  The screening copy and its norms hold 64 padding rows past
-  // the last cloud, so a tile never reads outside them (rows past a cloud
-  // never enter a list).  Every thread issues NKB + 1 loads per tile, which
-  // keeps the vmcnt bookkeeping static.
+  // every tile.  The screening copy and its norms hold at least BN padding
+  // rows past the last cloud, so a tile never reads outside them (rows past a
+  // cloud never enter a list).  Every thread issues NKB + 1 loads per tile
+  // (wave w loads the norms of rows 64 (w mod BN/64) + lane), which keeps the
+  // vmcnt bookkeeping static.
   // Scan order: tiles tstart, tstart + 1, ... cyclically.  With a spatial
   // order (perm != null: rows of Xq are the points perm[.], grouped by
   // nearest pivot) tstart is the tile of the block's own first query, so the
@@ -81,7 +98,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
   unsigned voff[NKB];
 #pragma unroll
   for (int i = 0; i < NKB; ++i) {
-    const int p = tid + 256 * i;
+    const int p = tid + NT * i;
     const int r = p / cpr, sc = p - r * cpr;
     voff[i] = (unsigned)(r * RS + ((sc ^ (r & smask)) << 4));
   }
@@ -92,9 +109,11 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     const char* tb = Xb + (int64_t)t0 * RS;
 #pragma unroll
     for (int i = 0; i < NKB; ++i)
-      __builtin_amdgcn_global_load_lds((gptr_t)(tb + voff[i]), (lptr_t)(stage + (256 * i + 64 * wave) * 16),
+      __builtin_amdgcn_global_load_lds((gptr_t)(tb + voff[i]), (lptr_t)(stage + (NT * i + 64 * wave) * 16),
                                        16, 0, 0);
-    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + lane), (lptr_t)(stage + TILE), 4, 0, 0);
+    const int nh = wave % (BN / 64);
+    __builtin_amdgcn_global_load_lds((gptr_t)(nq + t0 + 64 * nh + lane), (lptr_t)(stage + TILE + 256 * nh), 4, 0,
+                                     0);
   };
   // one tile consumed by every thread: wait for the next tile's loads, let
   // every wave pass, and refill the stage the consumed tile used
@@ -104,7 +123,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     issue((it + PIPE - 1) & (PIPE - 1));    // into the stage tile it-1 used
   };
 
-  // Products of one half (32 rows) of a tile: the accumulators start at the
+  // Products of one 32-row group jh of a tile: the accumulators start at the
   // norms of their rows; A fragments double-buffered (the LDS reads of
   // K-step kb + 1 are issued before the products of K-step kb).
   auto products = [&](const char* tile, int jh, f32x4 (&acc)[QB][2]) {
@@ -152,7 +171,7 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
       }
     }
   };
-  // Screening filter of one half: lane holds rows t0h + jj*16 + 4g + r,
+  // Screening filter of one group: lane holds rows t0h + jj*16 + 4g + r,
   // query qb*16 + i16.
   auto filter = [&](const f32x4 (&acc)[QB][2], int t0h) {
     unsigned qbmask = 0;
@@ -169,9 +188,10 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
                          t0h, bd.c1, wq0, lane, g, i16);
   };
 
-  // Software pipeline over halves: the products of the next half are issued
-  // before the filter (and any insertion) of the current one, so the matrix
-  // cores stay busy meanwhile.
+  // Software pipeline over 32-row groups: the products of the next group
+  // are issued before the filter (and any insertion) of the current one, so
+  // the matrix cores stay busy meanwhile.  Group h of a tile accumulates in
+  // accA for even h, accB for odd h.
 #pragma unroll
   for (int it = 0; it < PIPE - 1; ++it) issue(it);
   f32x4 accA[QB][2], accB[QB][2];
@@ -185,13 +205,20 @@ __global__ __launch_bounds__(256, 2) void dist_topk_v2_kernel(
     const char* tile = smem + (it & (PIPE - 1)) * STG;
     const int t0 = bd.c0 + tc * BN;
     tc = tc + 1 == ntile ? 0 : tc + 1;
-    products(tile, 1, accB);
-    if (it > 0) filter(accA, t0);
+#pragma unroll
+    for (int h = 1; h < GR; h += 2) {
+      products(tile, h, accB);
+      if (it > 0 || h > 1) filter(accA, t0 + 32 * (h - 1));
+      if (h + 1 < GR) {
+        products(tile, h + 1, accA);
+        filter(accB, t0 + 32 * h);
+      }
+    }
     if (it + 1 < ntile) {
       next_tile(it + 1);
       products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
     }
-    filter(accB, t0 + 32);
+    filter(accB, t0 + 32 * (GR - 1));
   }
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 

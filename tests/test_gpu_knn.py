@@ -210,6 +210,69 @@ def test_knn_streamed_spatial_order_sampled_rows(prec, d):
     assert np.all(np.diff(srt, axis=1) > 0) and np.all(nbr != np.arange(n)[:, None])
 
 
+# From 2,097,152 points in one cloud the pipelined kernel runs eight waves of
+# 64 queries per block over tiles of 128 rows (512 queries per block): a
+# ragged last tile and block, three K-block counts (bf16 d = 32, 96; float32
+# d = 40; d = 128 in the test below), in the spatial order, and a batch whose
+# small clouds share the launch with one large cloud (no spatial order
+# there); sampled rows against the oracle.  The bf16 cases take integer
+# coordinates (exact in bf16), so that exact mode certifies almost every row
+# and the recomputation of the rest stays cheap at this size.
+@pytest.mark.parametrize("prec,d,batched", [("bf16", 96, False), ("fp32", 40, False), ("bf16", 32, True)])
+def test_knn_eight_wave_blocks_sampled_rows(prec, d, batched):
+    k = 20 if d >= 96 else 10
+    if batched:
+        sizes = np.array([300, 2_100_000, 1000, 777])
+        X, offs = datagen.clouds(n_clouds=len(sizes), d=d, seed=5, sizes=sizes)
+        X = np.round(X * 8.0).astype(np.float32)
+    elif prec == "bf16":
+        X, offs = datagen.gamma_int(n=2_100_001, d=d, seed=d + 1), None
+    else:
+        X, offs = datagen.blobs(n=2_100_001, d=d, n_clusters=20, seed=d + 1), None
+    n = len(X)
+    print(f"case n={n} d={d} k={k} {prec} eight-wave blocks batched={batched}", flush=True)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True, **({"offs": offs} if batched else {}))
+    print("stats", st, flush=True)
+    rng = np.random.default_rng(d)
+    rows = np.unique(np.concatenate([rng.choice(n, size=40, replace=False), [0, n - 1]]))
+    if batched:
+        rows = np.unique(np.concatenate([rows, offs[:-1], offs[1:] - 1, np.arange(300, 340)]))
+        for b in range(len(sizes)):
+            rb = rows[(rows >= offs[b]) & (rows < offs[b + 1])]
+            if len(rb) == 0:
+                continue
+            Xb = X[offs[b]:offs[b + 1]]
+            ref_n, ref_s = oracle.knn_exact(Xb, k, rows=rb - offs[b], block=32)
+            for i, r in enumerate(rb):
+                assert set(nbr[r].tolist()) == set((ref_n[i] + offs[b]).tolist()), (r, nbr[r], ref_n[i] + offs[b])
+            np.testing.assert_allclose(np.sort(dist[rb], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5,
+                                       atol=1e-6)
+    else:
+        ref_n, ref_s = oracle.knn_exact(X, k, rows=rows, block=32)
+        for i, r in enumerate(rows):
+            assert set(nbr[r].tolist()) == set(ref_n[i].tolist()), (r, nbr[r], ref_n[i])
+        np.testing.assert_allclose(np.sort(dist[rows], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5,
+                                   atol=1e-6)
+    assert np.all(np.diff(dist, axis=1) >= 0)
+    srt = np.sort(nbr, axis=1)
+    assert np.all(np.diff(srt, axis=1) > 0) and np.all(nbr != np.arange(n)[:, None])
+
+
+def test_knn_eight_wave_blocks_integer_data_bf16_equals_fp32():
+    """Integer-valued features (exact in bf16): the bf16-screened lists equal
+    the float32 ones entry for entry on the eight-wave kernel, and sampled rows
+    equal the oracle's."""
+    X = datagen.gamma_int(n=2_100_000, d=128, seed=4)
+    print("case gamma-int n=2100000 d=128 k=20 bf16 vs fp32", flush=True)
+    nb, db, _ = _run(X, 20, precision="bf16")
+    nf, df, _ = _run(X, 20, precision="fp32", exact=True)
+    assert np.array_equal(nb, nf) and np.array_equal(db, df)
+    rows = np.sort(np.random.default_rng(2).choice(len(X), size=24, replace=False))
+    ref_n, ref_s = oracle.knn_exact(X, 20, rows=rows, block=8)
+    for i, r in enumerate(rows):
+        assert set(nf[r].tolist()) == set(ref_n[i].tolist()), (r, nf[r], ref_n[i])
+
+
 # k above 24 takes candidate lists of k' = 64: the LDS-list kernel up to 256
 # dimensions (bf16) or 128 (fp32), also with fewer K-blocks than its
 # template holds (d = 200 bf16, d = 100 fp32: 7 of 8), the K-chunked kernel

@@ -148,3 +148,43 @@ def test_connect_capacity_reports_required_size_and_keeps_labels():
     assert torch.equal(comp, G_ref.comp) and n_col.value == G_ref.col.numel()
     assert torch.equal(row_ptr, G_ref.row_ptr) and torch.equal(col[:n_col.value], G_ref.col)
     assert bool(torch.all(eu == -9)) and bool(torch.all(ew == -9.0))
+
+
+def test_dense_fused_smaller_workspace_runs_cloud_groups():
+    """d <= 64: the size query covers every cloud's pair matrix; a workspace
+    that holds only the largest matrix (plus the fixed part) runs the clouds
+    in consecutive groups with the same results, and one byte less is
+    rejected."""
+    lib = L.load()
+    X, offs = datagen.clouds(n_clouds=9, lo=100, hi=700, d=64, seed=12)
+    n, d, B = X.shape[0], X.shape[1], len(offs) - 1
+    Xd = torch.from_numpy(X).to(DEV)
+    ref = F.mst_dense_fused(Xd, offs=offs)
+    torch.cuda.synchronize()
+    sizes = np.diff(offs)
+    o = np.ascontiguousarray(offs, dtype=np.int64)
+    op = o.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    outs = [torch.empty(n - B, dtype=torch.int32, device=DEV), torch.empty(n - B, dtype=torch.int32, device=DEV),
+            torch.empty(n - B, device=DEV), torch.empty(B, device=DEV), torch.empty_like(Xd)]
+    s = A._stream()
+    sz = ctypes.c_size_t(0)
+    assert lib.famst_mst_dense_fused(_p(Xd), n, d, op, B, *[_p(t) for t in outs], None, ctypes.byref(sz), s) == 0
+    full = sz.value
+    mat = int((sizes.astype(np.int64) ** 2).sum()) * 4
+    fixed = full - ((mat + 255) // 256) * 256
+    small = fixed + int(sizes.max()) ** 2 * 4
+    print("workspace full", full, "smallest accepted", small, flush=True)
+    assert small < full // 2
+    ws = torch.empty(full, dtype=torch.uint8, device=DEV)
+    short = ctypes.c_size_t(small - 1)
+    assert lib.famst_mst_dense_fused(_p(Xd), n, d, op, B, *[_p(t) for t in outs], _p(ws), ctypes.byref(short),
+                                     s) == L.FAMST_EWORKSPACE
+    for w in (small, small + 3 * 700 * 700):
+        for t in outs:
+            t.fill_(-5)
+        ws_sz = ctypes.c_size_t(w)
+        assert lib.famst_mst_dense_fused(_p(Xd), n, d, op, B, *[_p(t) for t in outs], _p(ws), ctypes.byref(ws_sz),
+                                         s) == 0
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b)
