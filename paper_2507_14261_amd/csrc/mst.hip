@@ -281,7 +281,6 @@ __global__ __launch_bounds__(256) void tree_weight_kernel(const float* __restric
 constexpr int PRIM_MAX = 16384;   // local ids fit in 14 bits
 constexpr int PRIM_NT = 512;      // threads per cloud
 constexpr int PRIM_NT_DM = 1024;  // threads per cloud, Prim over the pair matrices
-constexpr int PRIM_RD = 8;        // matrix entries in flight per thread while the list is long
 
 __device__ __forceinline__ bool ekey_less(float w1, int a1, int b1, float w2, int a2, int b2) {
   int l1 = min(a1, b1), h1 = max(a1, b1), l2 = min(a2, b2), h2 = max(a2, b2);
@@ -390,17 +389,16 @@ __device__ __forceinline__ uint64_t prim_relax(uint64_t key, float s, int cur) {
 // front (their order does not matter: the minimum is over unique keys).
 // emit(step, p, j, w) is called by thread 0 for each edge, in insertion
 // order.  VEC: d == 64 and rows 16-byte aligned; FAMST_PRIM_R rows per
-// quad are in flight.  CMAX >= nb / NT.  DM: squared distances from the
-// cloud's pair matrix Dc (row-major nb x nb) instead.
+// quad are in flight.  CMAX >= nb / NT.
 constexpr int PRIM_COMPACT = 32;
 
 #ifndef FAMST_PRIM_R
 #define FAMST_PRIM_R 8
 #endif
-template <int NT, bool VEC, int CMAX, bool DM = false, class Emit>
+template <int NT, bool VEC, int CMAX, class Emit>
 __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int nb,
                            uint64_t* __restrict__ keys, uint64_t* __restrict__ wkeys,
-                           int* __restrict__ mcount, Emit emit, const float* __restrict__ Dc = nullptr) {
+                           int* __restrict__ mcount, Emit emit) {
   constexpr int NW = NT / 64, NQ = NT / 4, R = FAMST_PRIM_R;   // rows in flight per lane
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, c = t & 3, g = t >> 2;
   // vertex 0 starts the tree; every other vertex has the placeholder edge
@@ -414,41 +412,7 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
     const float* __restrict__ xc = X + (c0 + cur) * d;
     uint64_t best = PRIM_DEAD;
     int bslot = -1;
-    if constexpr (DM) {
-      // one thread per list slot: the squared distances to the newest
-      // vertex are row cur of the cloud's matrix (dead slots read its
-      // diagonal, so the loads need no branches); RD slots per thread are in
-      // flight at once, fewer as the list shrinks
-      const float* __restrict__ dr = Dc + (int64_t)cur * nb;
-      auto relax_slots = [&](auto rd) {
-        constexpr int RD = decltype(rd)::value;
-        for (int q0 = t; q0 < m; q0 += NT * RD) {
-          uint64_t kk[RD];
-          float sq[RD];
-#pragma unroll
-          for (int u = 0; u < RD; ++u) {
-            const int q = q0 + u * NT;
-            kk[u] = q < m ? keys[q] : PRIM_DEAD;
-            sq[u] = dr[kk[u] != PRIM_DEAD ? key_j(kk[u]) : cur];
-          }
-#pragma unroll
-          for (int u = 0; u < RD; ++u) {
-            if (kk[u] != PRIM_DEAD) {
-              const uint64_t nk = prim_relax(kk[u], sq[u], cur);
-              const int q = q0 + u * NT;
-              if (nk != kk[u]) keys[q] = nk;
-              if (nk < best) {
-                best = nk;
-                bslot = q;
-              }
-            }
-          }
-        }
-      };
-      if (m > 4 * NT) relax_slots(std::integral_constant<int, PRIM_RD>{});
-      else if (m > NT) relax_slots(std::integral_constant<int, 4>{});
-      else relax_slots(std::integral_constant<int, 1>{});
-    } else if constexpr (VEC) {
+    if constexpr (VEC) {
       f32x4 xa[4];
 #pragma unroll
       for (int mm = 0; mm < 4; ++mm) xa[mm] = reinterpret_cast<const f32x4*>(xc)[c + 4 * mm];
@@ -514,7 +478,7 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
     for (int w = 1; w < NW; ++w) gb = wk[w] < gb ? wk[w] : gb;
     const int j = key_j(gb), p = key_p(gb);
     if (t == 0) emit(step, p, j, key_w(gb));
-    if (best == gb && (DM || c == 0)) keys[bslot] = PRIM_DEAD;   // the slot's one owner
+    if (best == gb && c == 0) keys[bslot] = PRIM_DEAD;
     cur = __builtin_amdgcn_readfirstlane(j);
     if (step % PRIM_COMPACT == 0 && step + 1 < nb) {
       if (t == 0) *mcount = 0;
@@ -535,6 +499,73 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
       __syncthreads();
       m = *mcount;
     }
+  }
+  __syncthreads();
+}
+
+// Dense Prim over the cloud's pair matrix Dc (row-major nb x nb squared
+// distances) by NT threads.  Vertex v >= 1 sits in slot v - 1 for the whole
+// run, as entry (v - 1) / NT of thread (v - 1) mod NT, with its key and the
+// square below which a distance can change that key (w0^2 (1 + 2^-20), as
+// in prim_relax) in registers: a step reads row cur of the matrix with
+// consecutive lanes on consecutive entries and compares; only entries under
+// the square take the exact relaxation, and slots of tree vertices are
+// skipped (no compaction: it would scatter the row reads).  Same keys, same
+// minimum and the same emit order as prim_cloud, so the same tree.
+template <int NT, int CMAX, class Emit>
+__device__ void prim_cloud_dm(const float* __restrict__ Dc, int nb, uint64_t* __restrict__ wkeys, Emit emit) {
+  static_assert((NT & (NT - 1)) == 0 && NT >= 64, "slot owners by mask");
+  constexpr int NW = NT / 64;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint64_t kr[CMAX];
+  float thr[CMAX];
+  auto set_slot = [&](int i, uint64_t k) {
+    kr[i] = k;
+    const float w0 = key_w(k);
+    // relax unless s > thr (prim_relax's early exit; none for tiny w0)
+    thr[i] = (k != PRIM_DEAD && w0 > 1e-18f) ? w0 * w0 * 1.00000095f : F_INF;
+  };
+  // vertex 0 starts the tree; every other vertex has the placeholder edge
+  // (+inf, 0, v), replaced in the first step
+#pragma unroll
+  for (int i = 0; i < CMAX; ++i) {
+    const int v = t + NT * i + 1;
+    set_slot(i, v < nb ? prim_key(F_INF, 0, v) : PRIM_DEAD);
+  }
+  int cur = 0;
+  for (int step = 1; step < nb; ++step) {
+    const float* __restrict__ dr = Dc + (int64_t)cur * nb;
+    float sq[CMAX];
+#pragma unroll
+    for (int i = 0; i < CMAX; ++i) {
+      const int v = t + NT * i + 1;
+      if (NT * i + 1 < nb) sq[i] = dr[v < nb ? v : cur];
+    }
+    uint64_t best = PRIM_DEAD;
+#pragma unroll
+    for (int i = 0; i < CMAX; ++i) {
+      if (NT * i + 1 < nb) {
+        if (!(sq[i] > thr[i]) && kr[i] != PRIM_DEAD) set_slot(i, prim_relax(kr[i], sq[i], cur));
+        best = kr[i] < best ? kr[i] : best;
+      }
+    }
+    const uint64_t wb = wave_min_u64(best);
+    uint64_t* wk = wkeys + (step & 1) * NW;
+    if (lane == 0) wk[wave] = wb;
+    __syncthreads();
+    uint64_t gb = wk[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) gb = wk[w] < gb ? wk[w] : gb;
+    const int j = key_j(gb), p = key_p(gb);
+    if (t == 0) emit(step, p, j, key_w(gb));
+    // the owner of the new tree vertex retires its slot
+    const int jq = j - 1;
+    if ((jq & (NT - 1)) == t) {
+#pragma unroll
+      for (int i = 0; i < CMAX; ++i)
+        if (i == jq / NT) set_slot(i, PRIM_DEAD);
+    }
+    cur = __builtin_amdgcn_readfirstlane(j);
   }
   __syncthreads();
 }
@@ -752,8 +783,8 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
       ow[eo + step - 1] = w;
     };
     constexpr int CM = FUSED_MAX / NT;
-    prim_cloud<NT, MODE == 1, CM, MODE == 2>(X, d, c0, nb, keys, wkeys, &mcount, emit,
-                                             MODE == 2 ? D + dmoff[b] : nullptr);
+    if constexpr (MODE == 2) prim_cloud_dm<NT, CM>(D + dmoff[b], nb, wkeys, emit);
+    else prim_cloud<NT, MODE == 1, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
     __threadfence_block();
     __syncthreads();
     // ---- tree weight, compensated, in insertion order

@@ -169,6 +169,34 @@ def test_dense_fused_persistent_batch_matches_oracle():
     assert np.array_equal(G, G2)
 
 
+@pytest.mark.parametrize("d", [16, 64])
+def test_dense_fused_ties_and_duplicates_match_unfused_prim(d):
+    """Exact ties everywhere: integer coordinates, duplicated rows and a cloud
+    of identical points (every edge weighs 0, so ids alone decide).  The pair
+    matrix path gives the same tree as the unfused dense Prim (which computes
+    each distance on the fly) and the oracle's weight."""
+    rng = np.random.default_rng(d)
+    parts = []
+    for m in (300, 517, 64, 900):
+        Y = rng.integers(0, 3, size=(m, d)).astype(np.float32)
+        Y[m // 2:] = Y[: m - m // 2]   # second half duplicates the first
+        parts.append(Y)
+    parts.append(np.full((130, d), 2.5, dtype=np.float32))
+    X = np.concatenate(parts)
+    offs = np.concatenate([[0], np.cumsum([len(q) for q in parts])]).astype(np.int64)
+    print(f"case dense fused ties d={d} sizes={np.diff(offs).tolist()}", flush=True)
+    Xd = _dev(X, torch.float32)
+    tu, tv, tw, W, G = (t.cpu().numpy() for t in F.mst_dense_fused(Xd, offs=offs))
+    a = F.mst(Xd, algo="prim", offs=offs)
+    assert sorted(zip(np.minimum(tu, tv).tolist(), np.maximum(tu, tv).tolist())) == \
+        sorted(zip(a[0].cpu().numpy().tolist(), a[1].cpu().numpy().tolist()))
+    for b in range(len(parts)):
+        sl = slice(offs[b], offs[b + 1])
+        ref = oracle.prim_exact(X[sl])
+        assert math.isclose(float(W[b]), ref[3], rel_tol=1e-6, abs_tol=1e-6)
+    assert float(W[-1]) == 0.0
+
+
 def test_gradient_famst_path_scaled_by_upstream():
     X = datagen.blobs(n=800, d=16, n_clusters=5, seed=3)
     Xd = _dev(X, torch.float32).requires_grad_(True)
