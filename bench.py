@@ -33,19 +33,19 @@ FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two f
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "02e3042a00c6048a7712f75a181fe12473bb86e9",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "560a8ce67fbfe05e91620fa531c8fe584433e953",
                     "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 967.409, "write_GB": 0.288,
+        "fetch_GB": 968.465, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("rerank", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "57494453dc8828ef70b687de24b33488132dde44",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "6170444ec5100da616f38413f05876b5678359aa",
                     "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5.268, "write_GB": 0.256,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("prep", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "57494453dc8828ef70b687de24b33488132dde44",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "6170444ec5100da616f38413f05876b5678359aa",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 0.512, "write_GB": 0.272,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
@@ -55,9 +55,14 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 1.704, "write_GB": 0.512,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "5a7f4347b68eaf06acc8836f66e8896534e37b7c",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "b691f102952c937032bfa19a75fc808fbc2768c3",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 803.092, "write_GB": 0.409,
+        "fetch_GB": 27.056, "write_GB": 0.310,
+        "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
+    ("pair_matrix", "clouds-256-d64"): {
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "b691f102952c937032bfa19a75fc808fbc2768c3",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 6.439, "write_GB": 28.851,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
 }
 
@@ -185,12 +190,11 @@ def bench_clouds(args, F, torch):
                 res[name]["phases"][ph] = round(pms / args.steps, 3)
     # exact path (d <= 64): the pair kernel evaluates each unordered pair once
     # (64 differences, 64 fused multiply-adds, 15 additions: 207 flops) and
-    # stores both orders; each Prim step then reads one matrix entry per
-    # vertex outside the tree, so one Prim launch reads every pair's entry
-    # once: sum_i n_i (n_i - 1) / 2 floats
+    # stores both orders (sum_i n_i^2 floats); each of the n_i - 1 Prim steps
+    # of a cloud reads the n_i - 1 off-root entries of one matrix row
     sizes = np.diff(offs).astype(np.float64)
     pairs = float(np.sum(sizes * (sizes - 1) / 2))
-    prim_bytes = pairs * 4
+    prim_bytes = float(np.sum((sizes - 1) ** 2)) * 4
     pair_flops = pairs * 207
     # weight error of the k = 16 FAMST trees against the exact trees, per cloud
     W_exact = last["exact"][3].double().cpu().numpy()
@@ -224,6 +228,7 @@ def bench_clouds(args, F, torch):
                      "avg_ms": round(ex["kernel_avg_ms"], 3) if ex["kernel_avg_ms"] else None,
                      "algorithmic_GB": round(prim_bytes / 1e9, 3),
                      "note": "sequential Prim steps (one matrix row each): bound by per-step latency, not by HBM"},
+        "pair_matrix_traffic_GB": measured_traffic("pair_matrix", "clouds-256-d64"),
         "pair_matrix": {"bound": "alu", "ms_per_launch": pm_ms,
                         "achieved": round(pair_flops / (pm_ms * 1e-3) / 1e12, 2) if pm_ms else None,
                         "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",

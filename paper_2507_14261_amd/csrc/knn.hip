@@ -1022,6 +1022,13 @@ static_assert(HdShape<4>::BN <= PADR && HdShape<8>::BN <= PADR && hd_qblk<4>() <
                   V2Shape<8>::BN <= PADR,
               "padding covers every streamed tile and query block");
 
+// Spatial order of the scan for one cloud from this many points: the early
+// tight thresholds cut the list insertions (10K x 32 blobs: the screening
+// 4.8 -> 2.0 ms in float32, 7.0 -> 2.6 ms in bf16).  Not for batches: with
+// pivots per cloud the 256 clouds of 64-dimensional Gaussian clusters took
+// 32.8 ms against 22.9 ms in index order.
+static constexpr int64_t SPATIAL_MIN = 4096;
+
 // Eight-wave blocks of the pipelined kernel from this many rows of one cloud
 // on: they halve the rows streamed per query, which pays where the stream is
 // longest (4M x 96: 9 % faster) but not at 1M x 128 (15 % slower: the wider
@@ -1314,7 +1321,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   // spatial order of the scan (one large cloud, pipelined or streamed
   // screening; the streamed one assigns pivots on a 128-coordinate sketch)
   const bool spatial =
-      (p.piped || (p.hd && (int64_t)p.DP * esz <= FAMST_HD_SPATIAL_MAXB)) && B == 1 && n >= 32768;
+      (p.piped || (p.hd && (int64_t)p.DP * esz <= FAMST_HD_SPATIAL_MAXB)) && B == 1 && n >= SPATIAL_MIN;
   const size_t sn = spatial ? (size_t)n : 0;
   const size_t skn = spatial && p.hd ? (size_t)n : 0;
   uint16_t* skx = cv.take<uint16_t>(skn * 128);

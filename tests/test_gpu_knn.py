@@ -189,7 +189,7 @@ def test_knn_fp8_batched_clouds():
             assert set(got[i].tolist()) == set(ref_n[i].tolist())
 
 
-# One cloud of at least 32768 points on the streamed kernel: the rows are
+# One cloud of at least 4096 points on the streamed kernel: the rows are
 # visited in a spatial order (pivots assigned on a 128-coordinate sketch),
 # and the results are mapped back to the input order.
 @pytest.mark.parametrize("prec,d", [("bf16", 200), ("fp32", 100), ("fp8", 128), ("fp8", 300)])
@@ -271,6 +271,37 @@ def test_knn_eight_wave_blocks_integer_data_bf16_equals_fp32():
     ref_n, ref_s = oracle.knn_exact(X, 20, rows=rows, block=8)
     for i, r in enumerate(rows):
         assert set(nf[r].tolist()) == set(ref_n[i].tolist()), (r, nf[r], ref_n[i])
+
+
+# A batch of uneven clouds (one of 12 points) on the pipelined kernel, every
+# K-block count: every row of every cloud against the oracle, float32 and
+# bf16 in exact mode, and bf16 in the default mode against float32 on
+# integer coordinates.
+@pytest.mark.parametrize("prec,d", [("fp32", 24), ("bf16", 24), ("bf16", 100), ("fp32", 48)])
+def test_knn_batched_uneven_clouds_match_oracle(prec, d):
+    sizes = np.array([600, 3001, 12, 1500, 257, 2100])
+    X, offs = datagen.clouds(n_clouds=len(sizes), d=d, seed=d + 3, sizes=sizes)
+    k = 8
+    print(f"case batched {prec} d={d} sizes={sizes.tolist()}", flush=True)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True, offs=offs)
+    print("stats", st, flush=True)
+    for b in range(len(sizes)):
+        sl = slice(offs[b], offs[b + 1])
+        ref_n, ref_s = oracle.knn_exact(X[sl], k)
+        got = nbr[sl] - offs[b]
+        for i in range(len(got)):
+            assert set(got[i].tolist()) == set(ref_n[i].tolist()), (b, i, got[i], ref_n[i])
+        np.testing.assert_allclose(np.sort(dist[sl], axis=1), np.sqrt(np.sort(ref_s, axis=1)), rtol=1e-5,
+                                   atol=1e-6)
+
+
+def test_knn_batched_integer_bf16_equals_fp32():
+    sizes = np.array([5000, 333, 2700])
+    X, offs = datagen.clouds(n_clouds=len(sizes), d=40, seed=17, sizes=sizes)
+    X = np.round(X * 4.0).astype(np.float32)
+    nb, db, _ = _run(X, 10, precision="bf16", offs=offs)
+    nf, df, _ = _run(X, 10, precision="fp32", exact=True, offs=offs)
+    assert np.array_equal(nb, nf) and np.array_equal(db, df)
 
 
 # k above 24 takes candidate lists of k' = 64: the LDS-list kernel up to 256
