@@ -350,6 +350,17 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Minimum over lanes 0..15 of a row (the row shifts and bank steps of
+// wave_min_u64): lane 15 of every row holds its row's minimum.
+__device__ __forceinline__ uint64_t row16_min_u64(uint64_t v) {
+  v = dpp_min_step<0x111, 0xF, 0xF>(v);
+  v = dpp_min_step<0x112, 0xF, 0xF>(v);
+  v = dpp_min_step<0x113, 0xF, 0xF>(v);
+  v = dpp_min_step<0x114, 0xF, 0xE>(v);
+  v = dpp_min_step<0x118, 0xF, 0xC>(v);
+  return v;
+}
+
 // Selection key of a candidate edge (w, p, j), w >= 0, local ids < 2^14:
 // ordered as (w, min, max); the low bit says whether j (the vertex outside
 // the tree) is the smaller endpoint.  ~0 marks a dead list entry.
@@ -510,11 +521,13 @@ __device__ void prim_cloud(const float* __restrict__ X, int d, int64_t c0, int n
 // in prim_relax) in registers: a step reads row cur of the matrix with
 // consecutive lanes on consecutive entries and compares; only entries under
 // the square take the exact relaxation, and slots of tree vertices are
-// skipped (no compaction: it would scatter the row reads).  Same keys, same
-// minimum and the same emit order as prim_cloud, so the same tree.
+// retired (no compaction: it would scatter the row reads).  The matrices are
+// followed by FUSED_MAX zeroed floats, so the reads of the last slots stay
+// in the workspace.  Same keys, same minimum and the same emit order as
+// prim_cloud, so the same tree.
 template <int NT, int CMAX, class Emit>
 __device__ void prim_cloud_dm(const float* __restrict__ Dc, int nb, uint64_t* __restrict__ wkeys, Emit emit) {
-  static_assert((NT & (NT - 1)) == 0 && NT >= 64, "slot owners by mask");
+  static_assert((NT & (NT - 1)) == 0 && NT >= 64 && NT <= 1024, "slot owners by mask, 16 waves at most");
   constexpr int NW = NT / 64;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   uint64_t kr[CMAX];
@@ -522,8 +535,15 @@ __device__ void prim_cloud_dm(const float* __restrict__ Dc, int nb, uint64_t* __
   auto set_slot = [&](int i, uint64_t k) {
     kr[i] = k;
     const float w0 = key_w(k);
-    // relax unless s > thr (prim_relax's early exit; none for tiny w0)
-    thr[i] = (k != PRIM_DEAD && w0 > 1e-18f) ? w0 * w0 * 1.00000095f : F_INF;
+    // relax when s <= thr: prim_relax's early exit (none for tiny w0); never
+    // for a retired slot
+    thr[i] = k == PRIM_DEAD ? -F_INF : (w0 > 1e-18f ? w0 * w0 * 1.00000095f : F_INF);
+  };
+  auto slots_min = [&]() {
+    uint64_t b = PRIM_DEAD;
+#pragma unroll
+    for (int i = 0; i < CMAX; ++i) b = kr[i] < b ? kr[i] : b;
+    return b;
   };
   // vertex 0 starts the tree; every other vertex has the placeholder edge
   // (+inf, 0, v), replaced in the first step
@@ -532,39 +552,50 @@ __device__ void prim_cloud_dm(const float* __restrict__ Dc, int nb, uint64_t* __
     const int v = t + NT * i + 1;
     set_slot(i, v < nb ? prim_key(F_INF, 0, v) : PRIM_DEAD);
   }
-  int cur = 0;
+  // the thread's smallest key: keys only fall (relaxation) or retire (the
+  // owner of the new tree vertex recomputes it)
+  uint64_t best = slots_min();
+  int cur = 0, jq = -1;   // jq: the slot that the last step's tree vertex leaves
   for (int step = 1; step < nb; ++step) {
-    const float* __restrict__ dr = Dc + (int64_t)cur * nb;
+    // entries past the row's end read the next row or the zeroed padding
+    // after the last matrix: their slots are retired
+    const float* __restrict__ dr = Dc + (int64_t)cur * nb + t + 1;
     float sq[CMAX];
 #pragma unroll
-    for (int i = 0; i < CMAX; ++i) {
-      const int v = t + NT * i + 1;
-      if (NT * i + 1 < nb) sq[i] = dr[v < nb ? v : cur];
+    for (int i = 0; i < CMAX; ++i)
+      if (NT * i + 1 < nb) sq[i] = dr[NT * i];
+    // while the row is in flight: the owner of the last tree vertex retires
+    // its slot (it must not be relaxed below)
+    if (jq >= 0 && (jq & (NT - 1)) == t) {
+#pragma unroll
+      for (int i = 0; i < CMAX; ++i)
+        if (i == jq / NT) set_slot(i, PRIM_DEAD);
+      best = slots_min();
     }
-    uint64_t best = PRIM_DEAD;
 #pragma unroll
     for (int i = 0; i < CMAX; ++i) {
-      if (NT * i + 1 < nb) {
-        if (!(sq[i] > thr[i]) && kr[i] != PRIM_DEAD) set_slot(i, prim_relax(kr[i], sq[i], cur));
-        best = kr[i] < best ? kr[i] : best;
+      if (NT * i + 1 < nb && sq[i] <= thr[i]) {
+        const uint64_t nk = prim_relax(kr[i], sq[i], cur);
+        if (nk != kr[i]) {
+          set_slot(i, nk);
+          best = nk < best ? nk : best;
+        }
       }
     }
     const uint64_t wb = wave_min_u64(best);
     uint64_t* wk = wkeys + (step & 1) * NW;
     if (lane == 0) wk[wave] = wb;
     __syncthreads();
-    uint64_t gb = wk[0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) gb = wk[w] < gb ? wk[w] : gb;
+    // the NW wave minima: lane l of each wave takes minimum l mod 16 (NW <= 16)
+    const uint64_t gb = [&] {
+      const uint64_t m = row16_min_u64((lane & 15) < NW ? wk[lane & 15] : PRIM_DEAD);
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, 15);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), 15);
+      return ((uint64_t)hi << 32) | lo;
+    }();
     const int j = key_j(gb), p = key_p(gb);
     if (t == 0) emit(step, p, j, key_w(gb));
-    // the owner of the new tree vertex retires its slot
-    const int jq = j - 1;
-    if ((jq & (NT - 1)) == t) {
-#pragma unroll
-      for (int i = 0; i < CMAX; ++i)
-        if (i == jq / NT) set_slot(i, PRIM_DEAD);
-    }
+    jq = j - 1;
     cur = __builtin_amdgcn_readfirstlane(j);
   }
   __syncthreads();
@@ -1104,18 +1135,19 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   int64_t* dmoff_d = cv.take<int64_t>(dm ? B : 0);
   int64_t* tpre_d = cv.take<int64_t>(dm ? 2 * B + 1 : 0);
   const size_t fixed = cv.bytes();
-  float* D = cv.take<float>(dm ? mtot : 0);
+  // the matrices, then FUSED_MAX zeros that the last Prim slots may read
+  float* D = cv.take<float>(dm ? mtot + FUSED_MAX : 0);
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
   }
-  const size_t need = dm ? fixed + (size_t)mmax * 4 : cv.bytes();
+  const size_t need = dm ? fixed + (size_t)(mmax + FUSED_MAX) * 4 : cv.bytes();
   if (*ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return FAMST_EWORKSPACE;
   if (!X || !tu || !tv || !tw || !W || !grad_X) return FAMST_EINVAL;
   // groups of clouds (consecutive in the processing order) whose matrices fit
-  const int64_t cap = dm ? (int64_t)((*ws_bytes - fixed) / 4) : 0;
+  const int64_t cap = dm ? (int64_t)((*ws_bytes - fixed) / 4) - FUSED_MAX : 0;
   std::vector<int> gstart{0};
-  std::vector<int64_t> dmoff(dm ? B : 0), tpre;
+  std::vector<int64_t> dmoff(dm ? B : 0), tpre, gused;   // gused: matrix floats of each group
   if (dm) {
     int64_t used = 0, tiles = 0;
     tpre.push_back(0);
@@ -1124,6 +1156,7 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
       const int64_t nb = offs[b + 1] - offs[b], T = (nb + PD_T - 1) / PD_T;
       if (used + nb * nb > cap) {   // start a new group
         gstart.push_back(i);
+        gused.push_back(used);
         used = 0;
         tiles = 0;
         tpre.push_back(0);
@@ -1133,6 +1166,7 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
       tiles += T * (T + 1) / 2;
       tpre.push_back(tiles);
     }
+    gused.push_back(used);
   }
   gstart.push_back(B);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1155,6 +1189,7 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
       const int64_t ntile = tpre[g0 + gi + nc];
       FAMST_TRY(launch("pair_matrix", pair_matrix_kernel, dim3(stride_grid(ntile)), dim3(PD_NT), 0, s, X, d,
                        offs_d, order_d + g0, nc, tp, dmoff_d, D));
+      FAMST_HIP(hipMemsetAsync(D + gused[gi], 0, sizeof(float) * FUSED_MAX, s));
     }
     FAMST_HIP(hipMemsetAsync(queue, 0, sizeof(int), s));
     const dim3 grid(std::min(nc, ncu));
