@@ -55,14 +55,14 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 1.704, "write_GB": 0.512,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dense_prim_fused", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "b691f102952c937032bfa19a75fc808fbc2768c3",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "daa22cb5d901382d820b926f7f14e4af4f1750c0",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 27.056, "write_GB": 0.310,
+        "fetch_GB": 29.348, "write_GB": 0.311,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
     ("pair_matrix", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "b691f102952c937032bfa19a75fc808fbc2768c3",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "daa22cb5d901382d820b926f7f14e4af4f1750c0",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 6.439, "write_GB": 28.851,
+        "fetch_GB": 6.437, "write_GB": 28.852,
         "profile": "profiles/dense_prim_fused_clouds-256-d64_hbm_counters.md"},
 }
 
@@ -308,7 +308,7 @@ def bench_more_workloads(args, F, torch, pk):
     out["vmf-4m-d96"] = bench_workload(args, F, torch, "vmf-4m-d96", [("bf16", 2, 1), ("fp8", 1, 1)], pk)
     c = bench_clouds(args, F, torch)
     out["clouds-256-d64"] = {k2: c[k2] for k2 in ("value", "unit", "ms_per_step", "config", "roofline",
-                                                  "k16_path", "weight")}
+                                                  "pair_matrix", "pair_matrix_traffic_GB", "k16_path", "weight")}
     return out
 
 
