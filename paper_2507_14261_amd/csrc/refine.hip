@@ -1,9 +1,13 @@
 // Phase 3 of FAMST (Alg. 4): every inter-component edge (u, v) looks at the
 // neighbours of u in its own component for a closer endpoint to v, then at
 // the neighbours of v for a closer endpoint to the new u.  Rounds repeat
-// until no edge changes (Alg. 1).
+// until no edge changes (Alg. 1).  A round's update of an edge depends only
+// on X, the graph, the labels and the edge's own endpoints, so every edge
+// runs its rounds on its own, in one launch, until it stops changing; the
+// count of edges changed in round r is kept on the device.
+#include <vector>
+
 #include "famst_common.hpp"
-#include "prims.hpp"
 
 namespace famst {
 
@@ -153,45 +157,51 @@ __global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X
                                                     int32_t* __restrict__ eu, int32_t* __restrict__ ev,
                                                     float* __restrict__ ew,
                                                     const int32_t* __restrict__ ea,
-                                                    const int32_t* __restrict__ eb, int64_t ne,
-                                                    const int32_t* __restrict__ act_in,
-                                                    int64_t* __restrict__ changed_flag) {
+                                                    const int32_t* __restrict__ eb, int64_t ne, int max_rounds,
+                                                    unsigned long long* __restrict__ cnt) {
   __shared__ RefineSmem sm;
   if ((int64_t)blockIdx.x >= ne) return;
-  const int64_t e = act_in ? act_in[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t e = blockIdx.x;
   const int r16 = threadIdx.x & 15;
   const float tau = tau32(d);
-  const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
-  const float* xu = X + (int64_t)u * d;
-  const float* xv = X + (int64_t)v * d;
-  float ds = sq32_group(xu, xv, d, r16);
-  int us = u, vs = v;
-  // u side: neighbours of u in C_a, measured to v
-  bool u64;
-  double b64 = 0.0;
-  Best bu = row_argmin(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64, sm);
-  if (bu.s1 < F_INF &&
-      strictly_less(bu.s1, ds, X + (int64_t)bu.id1 * d, xv, xu, xv, d, tau, u64, b64)) {
-    us = bu.id1;
-    ds = bu.s1;
-  }
-  // v side: neighbours of v in C_b (excluding the original u), measured to u*
-  const float* xus = X + (int64_t)us * d;
-  Best bv = row_argmin(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64, sm);
-  if (bv.s1 < F_INF &&
-      strictly_less(bv.s1, ds, xus, X + (int64_t)bv.id1 * d, xus, X + (int64_t)vs * d, d, tau, u64,
-                    b64)) {
-    vs = bv.id1;
-    ds = bv.s1;
-  }
-  if (threadIdx.x == 0) {
-    const bool changed = us != u || vs != v;
-    if (changed) {
-      eu[e] = us;
-      ev[e] = vs;
-      ew[e] = __builtin_sqrtf(ds);
+  const int a = ea[e], b = eb[e];
+  int u = eu[e], v = ev[e];
+  float wn = 0.f;
+  bool any = false;
+  for (int r = 0; r < max_rounds; ++r) {   // every thread takes the same path
+    const float* xu = X + (int64_t)u * d;
+    const float* xv = X + (int64_t)v * d;
+    float ds = sq32_group(xu, xv, d, r16);
+    int us = u, vs = v;
+    // u side: neighbours of u in C_a, measured to v
+    bool u64;
+    double b64 = 0.0;
+    Best bu = row_argmin(X, d, row_ptr, col, comp, u, a, v, v, tau, &u64, &b64, sm);
+    if (bu.s1 < F_INF &&
+        strictly_less(bu.s1, ds, X + (int64_t)bu.id1 * d, xv, xu, xv, d, tau, u64, b64)) {
+      us = bu.id1;
+      ds = bu.s1;
     }
-    changed_flag[blockIdx.x] = changed ? 1 : 0;
+    // v side: neighbours of v in C_b (excluding the round's u), measured to u*
+    const float* xus = X + (int64_t)us * d;
+    Best bv = row_argmin(X, d, row_ptr, col, comp, v, b, u, us, tau, &u64, &b64, sm);
+    if (bv.s1 < F_INF &&
+        strictly_less(bv.s1, ds, xus, X + (int64_t)bv.id1 * d, xus, X + (int64_t)vs * d, d, tau, u64,
+                      b64)) {
+      vs = bv.id1;
+      ds = bv.s1;
+    }
+    if (us == u && vs == v) break;
+    if (threadIdx.x == 0) atomicAdd(&cnt[r], 1ull);
+    u = us;
+    v = vs;
+    wn = __builtin_sqrtf(ds);
+    any = true;
+  }
+  if (any && threadIdx.x == 0) {
+    eu[e] = u;
+    ev[e] = v;
+    ew[e] = wn;
   }
 }
 
@@ -264,16 +274,18 @@ __global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restri
                                                           float* __restrict__ ew,
                                                           const int32_t* __restrict__ ea,
                                                           const int32_t* __restrict__ eb, int64_t ne,
-                                                          const int32_t* __restrict__ act_in,
-                                                          int64_t* __restrict__ changed_flag) {
-  const int r16 = threadIdx.x & 15;
-  const int64_t slot = (int64_t)blockIdx.x * RG_EDGES + (threadIdx.x >> 4);
-  int64_t e = 0;
-  bool changed = false;
-  if (slot < ne) {
-    e = act_in ? act_in[slot] : slot;
-    const float tau = tau32(d);
-    const int u = eu[e], v = ev[e], a = ea[e], b = eb[e];
+                                                          int max_rounds, unsigned long long* __restrict__ cnt) {
+  const int r16 = threadIdx.x & 15, lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * RG_EDGES + (threadIdx.x >> 4);
+  if (e >= ne) return;   // whole groups
+  const float tau = tau32(d);
+  const int a = ea[e], b = eb[e];
+  int u = eu[e], v = ev[e];
+  float wn = 0.f;
+  bool any = false;
+  // the groups of a wave run their rounds in step: in iteration r every
+  // group still running is in its round r, so one atomic per wave counts
+  for (int r = 0; r < max_rounds; ++r) {
     const float* xu = X + (int64_t)u * d;
     const float* xv = X + (int64_t)v * d;
     float ds = sq32_group(xu, xv, d, r16);
@@ -294,27 +306,25 @@ __global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restri
       vs = bv.id1;
       ds = bv.s1;
     }
-    changed = us != u || vs != v;
-    if (r16 == 0) {
-      if (changed) {
-        eu[e] = us;
-        ev[e] = vs;
-        ew[e] = __builtin_sqrtf(ds);
-      }
-      changed_flag[slot] = changed ? 1 : 0;
-    }
+    const bool changed = us != u || vs != v;
+    const unsigned long long m = ballot(changed && r16 == 0);
+    if (m && lane == __builtin_ctzll(m)) atomicAdd(&cnt[r], (unsigned long long)__builtin_popcountll(m));
+    if (!changed) break;
+    u = us;
+    v = vs;
+    wn = __builtin_sqrtf(ds);
+    any = true;
+  }
+  if (any && r16 == 0) {
+    eu[e] = u;
+    ev[e] = v;
+    ew[e] = wn;
   }
 }
 
-// The next round's edge list: the edges whose flag is set, at their
-// exclusive-scan positions (no shared counter: one per changed edge would
-// serialise on a single address).
-__global__ __launch_bounds__(256) void refine_compact_kernel(const int64_t* __restrict__ flag,
-                                                            const int64_t* __restrict__ pos,
-                                                            const int32_t* __restrict__ act_in, int64_t nact,
-                                                            int32_t* __restrict__ act_out) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < nact && flag[i]) act_out[pos[i]] = act_in ? act_in[i] : (int32_t)i;
+__global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
 }
 
 }  // namespace famst
@@ -330,14 +340,8 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   if (n < 2 || d < 1 || n_edges < 0 || max_rounds < 1) return FAMST_EINVAL;
   if (n_edges >= (int64_t(1) << 31)) return FAMST_ENOTIMPL;
   Carve cv(ws);
-  // edges refined in a round: all in the first, then those the previous
-  // round changed (an unchanged edge stays unchanged: X, G and the labels
-  // are fixed); per-slot change flags, their exclusive scan, scan scratch
-  int32_t* act[2] = {cv.take<int32_t>(n_edges), cv.take<int32_t>(n_edges)};
-  int64_t* flag = cv.take<int64_t>(n_edges + 1);
-  int64_t* pos = cv.take<int64_t>(n_edges + 1);
-  const size_t tmpb = scan_i64_bytes((size_t)n_edges + 1);
-  void* tmp = cv.take<char>(tmpb);
+  // changed-edge count of every round
+  unsigned long long* cnt = cv.take<unsigned long long>(max_rounds);
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
@@ -346,29 +350,24 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   if (!rounds_run || (n_edges > 0 && (!X || !row_ptr || !col || !comp || !eu || !ev || !ew || !ea || !eb)))
     return FAMST_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  FAMST_TRY(launch("refine_zero", zero_u64_kernel, dim3(cdiv(max_rounds, 256)), dim3(256), 0, s, cnt, max_rounds));
+  if (n_edges >= FAMST_REFINE_GROUP_MIN)
+    FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(n_edges, RG_EDGES)), dim3(RNT), 0, s, X, d, row_ptr,
+                     col, comp, eu, ev, ew, ea, eb, n_edges, (int)max_rounds, cnt));
+  else if (n_edges > 0)
+    FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr, col, comp,
+                     eu, ev, ew, ea, eb, n_edges, (int)max_rounds, cnt));
+  std::vector<unsigned long long> hc(max_rounds);
+  FAMST_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned long long) * max_rounds, hipMemcpyDeviceToHost, s));
+  FAMST_HIP(hipStreamSynchronize(s));
+  // rounds until one changes nothing (a round after an empty one would be empty too)
   int r = 0;
   int64_t last = 0;
-  int64_t nact = n_edges;
-  const int32_t* ain = nullptr;   // null: every edge
   while (r < max_rounds) {
-    int32_t* aout = act[r & 1];
-    if (nact >= FAMST_REFINE_GROUP_MIN)
-      FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(nact, RG_EDGES)), dim3(RNT), 0, s, X, d,
-                       row_ptr, col, comp, eu, ev, ew, ea, eb, nact, ain, flag));
-    else
-      FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)nact), dim3(RNT), 0, s, X, d, row_ptr, col,
-                       comp, eu, ev, ew, ea, eb, nact, ain, flag));
-    FAMST_HIP(hipMemsetAsync(flag + nact, 0, sizeof(int64_t), s));
-    FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, (size_t)nact + 1, s));
-    FAMST_TRY(launch("refine_compact", refine_compact_kernel, dim3(cdiv(nact, 256)), dim3(256), 0, s, flag,
-                     pos, ain, nact, aout));
-    FAMST_HIP(hipMemcpyAsync(&last, pos + nact, sizeof(last), hipMemcpyDeviceToHost, s));
-    FAMST_HIP(hipStreamSynchronize(s));
-    if (deltas) deltas[r] = (int64_t)last;
+    last = (int64_t)hc[r];
+    if (deltas) deltas[r] = last;
     ++r;
     if (last == 0) break;
-    nact = last;
-    ain = aout;
   }
   *rounds_run = r;
   return last == 0 ? FAMST_OK : FAMST_WNOTCONVERGED;

@@ -179,6 +179,30 @@ def test_refine_multi_round_call_and_not_converged_warning():
     assert conv and deltas[-1] == 0 and rounds == len(deltas)
 
 
+@pytest.mark.parametrize("n,k,lam", [(1500, 1, 4), (3000, 1, 5)])
+def test_refine_one_call_equals_round_by_round(n, k, lam):
+    """All rounds in one call (every edge iterating on its own) give the same
+    endpoints, weights and per-round change counts as one call per round;
+    3000 points at k = 1 give over 32768 edges (the group-per-edge kernel)."""
+    X = datagen.blobs(n=n, d=32, n_clusters=10, seed=n)
+    nbr, _ = oracle.knn_exact(X, k)
+    Xd = _dev(X, torch.float32)
+    G, E = _connect(X, nbr, lam, 2)
+    E2 = F.Edges(*(t.clone() for t in (E.u, E.v, E.w, E.a, E.b)))
+    print(f"case refine one call n={n} k={k} lam={lam} edges={len(E.u)}", flush=True)
+    rounds, deltas, conv = F.refine(Xd, G, E, max_rounds=50)
+    assert conv
+    per = []
+    for _ in range(50):
+        r1, d1, _ = F.refine(Xd, G, E2, max_rounds=1)
+        per.append(d1[0])
+        if d1[0] == 0:
+            break
+    assert list(deltas) == per
+    for a, b in zip(_edges_np(E), _edges_np(E2)):
+        assert np.array_equal(a, b)
+
+
 def test_many_components_k1_sampled_pairs_and_edges():
     # the 10,000-point blobs with k = 1: about 1175 components, 6.9e5
     # component pairs and 1.7e7 lambda-samples.  Components are checked in
