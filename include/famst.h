@@ -189,13 +189,19 @@ int famst_connect(const float* X, int64_t n, int32_t d,
  *   v* = the neighbour v' of v in G with comp(v') == b, v' != u, that has
  *        the smallest (s(u*, v'), v'), taken only if it beats the length
  *        after the first step (strict).
- * Rounds repeat until no edge changes or max_rounds rounds ran.
+ * Rounds repeat until no edge changes or max_rounds rounds ran
+ * (1 <= max_rounds <= FAMST_REFINE_MAX_ROUNDS, else FAMST_EINVAL).  Since a
+ * round's update of an edge depends only on that edge's endpoints, every
+ * edge runs its own rounds until it stops changing, all in one launch, and
+ * the per-round counts are kept on the device; the workspace grows with
+ * max_rounds (2 KiB per round).
  *   eu, ev, ew  in/out (updated in place); ea, eb in
  *   rounds_run  host int32: rounds executed
  *   deltas      host int64 [max_rounds] or NULL: changed edges per round
  * Returns FAMST_WNOTCONVERGED if the last round still changed edges.
- * The stream is synchronised after every round.
+ * The stream is synchronised once, at the end.
  */
+#define FAMST_REFINE_MAX_ROUNDS 4096
 int famst_refine(const float* X, int64_t n, int32_t d,
                  const int64_t* row_ptr, const int32_t* col, const int32_t* comp,
                  int32_t* eu, int32_t* ev, float* ew,

@@ -28,6 +28,7 @@ FAMST_DENSE_PRIM = 2
 
 FAMST_NSTATS = 8
 FAMST_NOALLOC_SCRATCH_BYTES = 64 << 20
+FAMST_REFINE_MAX_ROUNDS = 4096
 
 EXPORTS = [
     "famst_strerror", "famst_version", "famst_knn_graph", "famst_connect", "famst_refine",

@@ -11,6 +11,12 @@
 
 namespace famst {
 
+// The changed-edge count of round r is spread over REFINE_CSLOTS counters
+// (by block index) and summed on the host: one counter per round would
+// serialise about a million atomics on one address in the first round of a
+// many-component input.
+constexpr int REFINE_CSLOTS = 256;
+
 struct Best {
   float s1;   // smallest s
   int id1;    // its id (smallest id among equal s)
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(RNT) void refine_kernel(const float* __restrict__ X
       ds = bv.s1;
     }
     if (us == u && vs == v) break;
-    if (threadIdx.x == 0) atomicAdd(&cnt[r], 1ull);
+    if (threadIdx.x == 0) atomicAdd(&cnt[r * REFINE_CSLOTS + (blockIdx.x & (REFINE_CSLOTS - 1))], 1ull);
     u = us;
     v = vs;
     wn = __builtin_sqrtf(ds);
@@ -308,7 +314,9 @@ __global__ __launch_bounds__(RNT) void refine_group_kernel(const float* __restri
     }
     const bool changed = us != u || vs != v;
     const unsigned long long m = ballot(changed && r16 == 0);
-    if (m && lane == __builtin_ctzll(m)) atomicAdd(&cnt[r], (unsigned long long)__builtin_popcountll(m));
+    if (m && lane == __builtin_ctzll(m))
+      atomicAdd(&cnt[r * REFINE_CSLOTS + (blockIdx.x & (REFINE_CSLOTS - 1))],
+                (unsigned long long)__builtin_popcountll(m));
     if (!changed) break;
     u = us;
     v = vs;
@@ -337,11 +345,12 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
                             int32_t max_rounds, int32_t* rounds_run, int64_t* deltas, void* ws,
                             size_t* ws_bytes, void* stream) {
   if (!ws_bytes) return FAMST_EINVAL;
-  if (n < 2 || d < 1 || n_edges < 0 || max_rounds < 1) return FAMST_EINVAL;
+  if (n < 2 || d < 1 || n_edges < 0 || max_rounds < 1 || max_rounds > FAMST_REFINE_MAX_ROUNDS) return FAMST_EINVAL;
   if (n_edges >= (int64_t(1) << 31)) return FAMST_ENOTIMPL;
   Carve cv(ws);
-  // changed-edge count of every round
-  unsigned long long* cnt = cv.take<unsigned long long>(max_rounds);
+  // changed-edge counts of every round (REFINE_CSLOTS per round)
+  const int ncnt = max_rounds * REFINE_CSLOTS;
+  unsigned long long* cnt = cv.take<unsigned long long>(ncnt);
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
@@ -350,16 +359,18 @@ extern "C" int famst_refine(const float* X, int64_t n, int32_t d, const int64_t*
   if (!rounds_run || (n_edges > 0 && (!X || !row_ptr || !col || !comp || !eu || !ev || !ew || !ea || !eb)))
     return FAMST_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  FAMST_TRY(launch("refine_zero", zero_u64_kernel, dim3(cdiv(max_rounds, 256)), dim3(256), 0, s, cnt, max_rounds));
+  FAMST_TRY(launch("refine_zero", zero_u64_kernel, dim3(cdiv(ncnt, 256)), dim3(256), 0, s, cnt, ncnt));
   if (n_edges >= FAMST_REFINE_GROUP_MIN)
     FAMST_TRY(launch("refine", refine_group_kernel, dim3(cdiv(n_edges, RG_EDGES)), dim3(RNT), 0, s, X, d, row_ptr,
                      col, comp, eu, ev, ew, ea, eb, n_edges, (int)max_rounds, cnt));
   else if (n_edges > 0)
     FAMST_TRY(launch("refine", refine_kernel, dim3((unsigned)n_edges), dim3(RNT), 0, s, X, d, row_ptr, col, comp,
                      eu, ev, ew, ea, eb, n_edges, (int)max_rounds, cnt));
-  std::vector<unsigned long long> hc(max_rounds);
-  FAMST_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned long long) * max_rounds, hipMemcpyDeviceToHost, s));
+  std::vector<unsigned long long> hs(ncnt), hc(max_rounds, 0);
+  FAMST_HIP(hipMemcpyAsync(hs.data(), cnt, sizeof(unsigned long long) * ncnt, hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
+  for (int r = 0; r < max_rounds; ++r)
+    for (int i = 0; i < REFINE_CSLOTS; ++i) hc[r] += hs[(size_t)r * REFINE_CSLOTS + i];
   // rounds until one changes nothing (a round after an empty one would be empty too)
   int r = 0;
   int64_t last = 0;

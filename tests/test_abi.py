@@ -60,7 +60,8 @@ def test_constants_match_header():
     for name in ["FAMST_OK", "FAMST_EINVAL", "FAMST_ECAPACITY", "FAMST_EDISCONNECTED", "FAMST_EHIP",
                  "FAMST_ENOTIMPL", "FAMST_ENONFINITE", "FAMST_EWORKSPACE", "FAMST_WNOTCONVERGED",
                  "FAMST_FP32", "FAMST_BF16", "FAMST_FP8_E4M3", "FAMST_EXACT", "FAMST_BORUVKA",
-                 "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS", "FAMST_NNDESCENT"]:
+                 "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS", "FAMST_NNDESCENT",
+                 "FAMST_REFINE_MAX_ROUNDS"]:
         m = re.search(r"#define\s+" + name + r"\s+\(?(-?\w+)\)?", txt)
         assert m, name
         assert int(m.group(1), 0) == getattr(L, name), name
@@ -76,6 +77,14 @@ def test_invalid_arguments_rejected_before_any_launch():
     assert lib.famst_knn_graph(None, 100, 4, None, 1, 5, 7, 0, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
     assert lib.famst_knn_graph(None, 100, 4, None, 1, 5, 0, 48, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
     assert lib.famst_refine(None, 100, 4, None, None, None, None, None, None, None, None, 0, 0, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    # the round cap, and a workspace that grows with the rounds
+    mr = L.FAMST_REFINE_MAX_ROUNDS
+    assert lib.famst_refine(None, 100, 4, None, None, None, None, None, None, None, None, 0, mr + 1, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
+    sizes = []
+    for rounds in (1, 10, mr):
+        assert lib.famst_refine(None, 100, 4, None, None, None, None, None, None, None, None, 0, rounds, None, None, None, ctypes.byref(sz), None) == L.FAMST_OK
+        sizes.append(sz.value)
+    assert sizes[0] < sizes[1] < sizes[2] <= (mr + 1) * 2048
     assert lib.famst_mst(None, 100, 4, None, 1, None, None, 0, None, None, None, 0, 9, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
     offs = (ctypes.c_int64 * 3)(0, 1, 100)   # a one-point cloud
     assert lib.famst_mst_backward(None, 100, 4, offs, 2, None, None, None, None, None, ctypes.byref(sz), None) == L.FAMST_EINVAL
