@@ -65,6 +65,10 @@ extern "C" {
                                      float32 distances would overflow        */
 #define FAMST_EWORKSPACE    (-7)  /* *ws_bytes smaller than required or ws
                                      misaligned                                */
+#define FAMST_ETIMEOUT      (-8)  /* a bounded wait inside a kernel ran out;
+                                     the outputs are not valid (a library
+                                     fault: it does not happen in a correct
+                                     build)                                    */
 #define FAMST_WNOTCONVERGED   1   /* refinement stopped at max_rounds with
                                      edges still changing                      */
 

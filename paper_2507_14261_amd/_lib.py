@@ -14,6 +14,7 @@ FAMST_EHIP = -4
 FAMST_ENOTIMPL = -5
 FAMST_ENONFINITE = -6
 FAMST_EWORKSPACE = -7
+FAMST_ETIMEOUT = -8
 FAMST_WNOTCONVERGED = 1
 
 FAMST_FP32 = 0

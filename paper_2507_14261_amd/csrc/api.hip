@@ -73,6 +73,7 @@ extern "C" const char* famst_strerror(int status) {
     case FAMST_ENOTIMPL: return "combination not supported";
     case FAMST_ENONFINITE: return "input holds a NaN or an infinity";
     case FAMST_EWORKSPACE: return "workspace too small or misaligned";
+    case FAMST_ETIMEOUT: return "a bounded wait inside a kernel ran out";
     case FAMST_WNOTCONVERGED: return "refinement stopped at max_rounds with edges still changing";
     default: return "unknown status";
   }

@@ -628,9 +628,9 @@ __global__ __launch_bounds__(PRIM_NT) void prim_kernel(const float* __restrict__
 // in the bits of sq32_group, and stored in both orders as the row-major
 // nb x nb matrix of the cloud at dmoff[b]; Prim then reads one matrix row
 // (4 bytes per vertex outside the tree) per step instead of the rows of
-// every such vertex (4 d bytes each).  One block per 64 x 64 tile of the
-// upper triangle of tiles; thread (ty, tx) holds the 16 pairs
-// (ty + 16 i, tx + 16 j).  The 16 chunk partials of a pair are combined as
+// every such vertex (4 d bytes each).  The matrix is built from 64 x 64
+// tiles of the upper triangle of tiles, 256 threads per tile; thread
+// (ty, tx) holds the 16 pairs (ty + 16 i, tx + 16 j).  The 16 chunk partials of a pair are combined as
 // sq32_group's xor butterfly (over 8, 4, 2, 1), i.e. a binary tree over the
 // chunks in bit-reversed order 0, 8, 4, 12, 2, ...; padding dimensions
 // (zero in both rows) leave a partial unchanged, as in sq32_group.
@@ -688,38 +688,30 @@ __device__ __forceinline__ void pd_pairs(const float* As, const float* Bs, int t
   }
 }
 
-__global__ __launch_bounds__(PD_NT) void pair_matrix_kernel(const float* __restrict__ X, int d,
-                                                            const int64_t* __restrict__ offs,
-                                                            const int* __restrict__ clouds, int nc,
-                                                            const int64_t* __restrict__ tpre,
-                                                            const int64_t* __restrict__ dmoff,
-                                                            float* __restrict__ D) {
-  __shared__ __attribute__((aligned(16))) float As[PD_T * PD_LD], Bs[PD_T * PD_LD];
-  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
-  const int64_t ntiles = tpre[nc];
-  for (int64_t gi = blockIdx.x; gi < ntiles; gi += gridDim.x) {
-    // cloud of the tile (tpre: prefix of the tile counts), then (ta, tb), ta <= tb
-    int lo = 0, hi = nc - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tpre[mid] <= gi) lo = mid;
-      else hi = mid - 1;
-    }
-    const int b = clouds[lo];
-    const int64_t c0 = offs[b];
-    const int nb = (int)(offs[b + 1] - c0);
-    const int T = (nb + PD_T - 1) / PD_T;
-    const int64_t li = gi - tpre[lo];
-    // row ta of the triangle starts at S(ta) = ta T - ta (ta - 1) / 2
-    int ta = (int)((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)li)) * 0.5);
+// One 64 x 64 tile (ta, tb), ta <= tb, of the upper triangle of tiles of a
+// cloud of nb rows starting at row c0, by 256 threads (t = 0 .. 255) with
+// their own As and Bs; the matrix of the cloud starts at Dm.  Every thread of
+// the block runs the same barriers whether or not its group has a tile
+// (valid), so groups of one block may hold tiles of different shapes.
+__device__ __forceinline__ void pair_tile(const float* __restrict__ X, int d, int64_t c0, int nb, int64_t li,
+                                          bool valid, float* __restrict__ As, float* __restrict__ Bs, int t,
+                                          float* __restrict__ Dm) {
+  const int ty = t >> 4, tx = t & 15;
+  const int T = (nb + PD_T - 1) / PD_T;
+  // row ta of the triangle starts at S(ta) = ta T - ta (ta - 1) / 2
+  auto S = [&](int r) { return (int64_t)r * T - (int64_t)r * (r - 1) / 2; };
+  int ta = 0, tb = 0;
+  if (valid) {
+    ta = (int)((2.0 * T + 1.0 - sqrt((2.0 * T + 1.0) * (2.0 * T + 1.0) - 8.0 * (double)li)) * 0.5);
     ta = max(0, min(ta, T - 1));
-    auto S = [&](int r) { return (int64_t)r * T - (int64_t)r * (r - 1) / 2; };
     while (ta > 0 && S(ta) > li) --ta;
     while (ta + 1 < T && S(ta + 1) <= li) ++ta;
-    const int tb = ta + (int)(li - S(ta));
-    const int a0 = ta * PD_T, b0 = tb * PD_T;
-    // rows of both tiles (rows past the cloud repeat its last row, dimensions
-    // past d are zero)
+    tb = ta + (int)(li - S(ta));
+  }
+  const int a0 = ta * PD_T, b0 = tb * PD_T;
+  // rows of both tiles (rows past the cloud repeat its last row, dimensions
+  // past d are zero)
+  if (valid)
     for (int e = t; e < PD_T * 16; e += PD_NT) {
       const int r = e >> 4, cc = e & 15;
       const int ra = min(a0 + r, nb - 1), rb = min(b0 + r, nb - 1);
@@ -733,14 +725,14 @@ __global__ __launch_bounds__(PD_NT) void pair_matrix_kernel(const float* __restr
       *reinterpret_cast<f32x4*>(As + r * PD_LD + 4 * cc) = va;
       *reinterpret_cast<f32x4*>(Bs + r * PD_LD + 4 * cc) = vb;
     }
-    __syncthreads();
-    float sq[16];
+  __syncthreads();
+  float sq[16];
+  if (valid) {
     pd_pairs(As, Bs, ty, tx, sq);
     // the values are complete here: the compiler would otherwise sink each
     // pair's arithmetic into its guarded store and read every chunk first
 #pragma unroll
     for (int p = 0; p < 16; ++p) __asm__ volatile("" : : "v"(sq[p]));
-    float* __restrict__ Dm = D + dmoff[b];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -748,41 +740,151 @@ __global__ __launch_bounds__(PD_NT) void pair_matrix_kernel(const float* __restr
         const int a = a0 + ty + 16 * i, c = b0 + tx + 16 * j;
         if (a < nb && c < nb) Dm[(int64_t)a * nb + c] = sq[4 * i + j];
       }
-    __syncthreads();   // the tile rows are read; As is reused for the transpose
-    if (ta != tb) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) As[(ty + 16 * i) * PD_LD + tx + 16 * j] = sq[4 * i + j];
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = b0 + ty + 16 * i, a = a0 + tx + 16 * j;
-          if (a < nb && c < nb) Dm[(int64_t)c * nb + a] = As[(tx + 16 * j) * PD_LD + ty + 16 * i];
-        }
-    }
-    __syncthreads();   // the next tile overwrites As and Bs
   }
+  __syncthreads();   // the tile rows are read; As is reused for the transpose
+  const bool mirror = valid && ta != tb;
+  if (mirror) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) As[(ty + 16 * i) * PD_LD + tx + 16 * j] = sq[4 * i + j];
+  }
+  __syncthreads();
+  if (mirror) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = b0 + ty + 16 * i, a = a0 + tx + 16 * j;
+        if (a < nb && c < nb) Dm[(int64_t)c * nb + a] = As[(tx + 16 * j) * PD_LD + ty + 16 * i];
+      }
+  }
+  __syncthreads();   // the next tile overwrites As and Bs
 }
 
-// Persistent exact-tree kernel for a batch of clouds: blocks pull clouds
-// from an atomic queue (largest first) and, for each, run dense Prim, the
-// compensated tree weight and the gradient rows of the cloud, all in one
-// launch.  Tree edges are written in Prim insertion order as (parent,
-// child).  The gradient of row v sums its parent edge first, then its
-// children in ascending order, so it is deterministic.
 constexpr int FUSED_MAX = 12288;
 
-// MODE: 0 distances on the fly (any d), 1 on the fly with 16-byte row loads
-// (d == 64), 2 from the pair matrices.
-template <int NT, int MODE>
+// After the tree of cloud b (rows c0 .. c0 + nb - 1, edges at eo .. eo + nb
+// - 2 in insertion order, par[v] the parent of v): the compensated tree
+// weight W[b] in insertion order, the children lists (stable in the child
+// id), and the gradient rows, one
+// 16-lane group per row: its parent edge first, then its children in
+// ascending id, so the result is deterministic.  endp and kid must not
+// overlap par.
+template <int NT>
+__device__ void cloud_tail(const float* __restrict__ X, int d, int64_t c0, int nb, int64_t eo, int b,
+                           const float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad,
+                           const int* __restrict__ par, int* __restrict__ endp, int* __restrict__ kid,
+                           float* __restrict__ ss, float* __restrict__ ee) {
+  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
+  constexpr int NG = NT / 16;
+  // ---- tree weight, compensated, in insertion order
+  {
+    float sacc = 0.f, cacc = 0.f;
+    for (int i = t; i < nb - 1; i += NT) {
+      float ns, err;
+      two_sum(sacc, ow[eo + i], ns, err);
+      sacc = ns;
+      cacc += err;
+    }
+    ss[t] = sacc;
+    ee[t] = cacc;
+    __syncthreads();
+    for (int w = NT / 2; w >= 1; w >>= 1) {
+      if (t < w) {
+        float ns, err;
+        two_sum(ss[t], ss[t + w], ns, err);
+        ss[t] = ns;
+        ee[t] = ee[t] + ee[t + w] + err;
+      }
+      __syncthreads();
+    }
+    if (t == 0) W[b] = ss[0] + ee[0];
+  }
+  // ---- children lists, stable in child id: counts by LDS atomics; then
+  // wave 0 scans them (lane l owns a contiguous stretch of parents) and
+  // places the children 64 ids at a time, each group of lanes with the same
+  // parent by one ballot (rank = lower lanes of the group), so endp[p] ends
+  // as the end of p's list
+  for (int j = t; j < nb; j += NT) endp[j] = 0;
+  __syncthreads();
+  for (int c = 1 + t; c < nb; c += NT) atomicAdd(&endp[par[c]], 1);
+  __syncthreads();
+  if (t < 64) {
+    const int lane = t, per = (nb + 63) / 64;
+    const int a = min(nb, lane * per), e = min(nb, a + per);
+    int sum = 0;
+    for (int p = a; p < e; ++p) sum += endp[p];
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    int run = incl - sum;
+    for (int p = a; p < e; ++p) {
+      const int cnt = endp[p];
+      endp[p] = run;
+      run += cnt;
+    }
+    for (int base = 1; base < nb; base += 64) {
+      const int c = base + lane;
+      const bool act = c < nb;
+      const int P = act ? par[c] : -1;
+      uint64_t todo = __ballot(act);
+      while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int P0 = __shfl(P, leader);
+        const uint64_t m = __ballot(act && P == P0);
+        const int start = endp[P0];
+        if (act && P == P0) kid[start + __popcll(m & ((1ull << lane) - 1))] = c;
+        if (lane == leader) endp[P0] = start + __popcll(m);
+        todo &= ~m;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- gradient rows, one 16-lane group per row
+  for (int v = grp; v < nb; v += NG) {
+    const float* xv = X + (c0 + v) * d;
+    float* out = grad + (c0 + v) * d;
+    const int k0 = v == 0 ? 0 : endp[v - 1], k1 = endp[v];
+    for (int t0 = 0; t0 < d; t0 += 16 * 8) {
+      float acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+      for (int e = (v == 0 ? k0 : k0 - 1); e < k1; ++e) {
+        const int o = (e < k0) ? par[v] : kid[e];
+        const float* xo = X + (c0 + o) * d;
+        float s = sq32_group(xv, xo, d, r16);
+        if (s == 0.f) continue;
+        float w = __builtin_sqrtf(s);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          int tt = t0 + q * 16 + r16;
+          if (tt < d) acc[q] += (xv[tt] - xo[tt]) / w;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int tt = t0 + q * 16 + r16;
+        if (tt < d) out[tt] = acc[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Persistent exact-tree kernel for a batch of clouds (d > 64): blocks pull
+// clouds from an atomic queue (largest first) and, for each, run dense Prim
+// with the distances on the fly, then cloud_tail, all in one launch.  Tree
+// edges are written in Prim insertion order as (parent, child).  VEC: d ==
+// 64 and rows 16-byte aligned.
+template <int NT, bool VEC>
 __global__ __launch_bounds__(NT) void prim_fused_kernel(
     const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
     int B, int* __restrict__ queue, int32_t* __restrict__ ou, int32_t* __restrict__ ov,
-    float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad, const float* __restrict__ D,
-    const int64_t* __restrict__ dmoff) {
+    float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(smem);              // Prim candidate list
   int* par = reinterpret_cast<int*>(keys + FUSED_MAX);            // tree parent of each vertex
@@ -791,8 +893,7 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
   __shared__ uint64_t wkeys[2 * NT / 64];
   __shared__ float ss[NT], ee[NT];
   __shared__ int cloud_s, mcount;
-  const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
-  constexpr int NG = NT / 16;
+  const int t = threadIdx.x;
   while (true) {
     if (t == 0) {
       int idx = atomicAdd(queue, 1);
@@ -805,7 +906,6 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
     const int64_t c0 = offs[b];
     const int nb = (int)(offs[b + 1] - c0);
     const int64_t eo = c0 - b;
-    // ---- dense Prim
     if (t == 0) par[0] = -1;
     auto emit = [&](int step, int p, int j, float w) {
       par[j] = p;
@@ -813,77 +913,135 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
       ov[eo + step - 1] = (int32_t)(c0 + j);
       ow[eo + step - 1] = w;
     };
-    constexpr int CM = FUSED_MAX / NT;
-    if constexpr (MODE == 2) prim_cloud_dm<NT, CM>(D + dmoff[b], nb, wkeys, emit);
-    else prim_cloud<NT, MODE == 1, CM>(X, d, c0, nb, keys, wkeys, &mcount, emit);
+    prim_cloud<NT, VEC, FUSED_MAX / NT>(X, d, c0, nb, keys, wkeys, &mcount, emit);
     __threadfence_block();
     __syncthreads();
-    // ---- tree weight, compensated, in insertion order
-    {
-      float sacc = 0.f, cacc = 0.f;
-      for (int i = t; i < nb - 1; i += NT) {
-        float ns, err;
-        two_sum(sacc, ow[eo + i], ns, err);
-        sacc = ns;
-        cacc += err;
-      }
-      ss[t] = sacc;
-      ee[t] = cacc;
-      __syncthreads();
-      for (int w = NT / 2; w >= 1; w >>= 1) {
-        if (t < w) {
-          float ns, err;
-          two_sum(ss[t], ss[t + w], ns, err);
-          ss[t] = ns;
-          ee[t] = ee[t] + ee[t + w] + err;
-        }
-        __syncthreads();
-      }
-      if (t == 0) W[b] = ss[0] + ee[0];
-    }
-    // ---- children lists by counting sort, stable in child id (one thread)
-    for (int j = t; j < nb; j += NT) endp[j] = 0;
-    __syncthreads();
+    cloud_tail<NT>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, ss, ee);
+  }
+}
+
+// Exact trees for d <= 64 in one persistent launch: the pair matrices and
+// Prim over them.  The work is a list of items taken from an atomic queue:
+// for each cloud, in the processing order (largest first), its tiles in
+// items of up to EXACT_TPI tiles, then one Prim item that runs
+// prim_cloud_dm over the finished matrix and cloud_tail.  A Prim item waits
+// until done[cpos] counts all tiles of its cloud.  The wait always ends:
+// every tile item of the cloud sits before it in the list, so it has been
+// taken by a block that is running, and tile items wait for nothing.  A
+// bounded spin (EXACT_SPIN_MAX sleeps) sets *err instead of waiting on.
+// Tiles publish their stores with one agent-scope release per item (an L2
+// write-back, costly enough that one per wave per item doubled the launch)
+// with the count; the Prim side reads the count and takes an agent-scope
+// acquire before its rows, so matrix rows written on another XCD are seen
+// (without the pair the trees come out wrong).  No path of the item loop leaves thread 0 out of a barrier
+// (a `continue` after its divergent update let the compiler send the other
+// threads round the loop without it).
+// Item (64 bits): cloud position << 32 | low; low == EXACT_PRIM: the Prim
+// item; else tiles s .. s + c of the cloud, low = s << EXACT_TPI_BITS | c.
+constexpr uint32_t EXACT_PRIM = 0x80000000u;
+constexpr int EXACT_TPI_BITS = 6, EXACT_TPI = 1 << EXACT_TPI_BITS;   // tiles per item at most
+// s_waitcnt immediate with vmcnt = 0 and no wait on the other counters
+constexpr int WAIT_VMCNT0 = 0x0F70;
+constexpr int EXACT_SPIN_MAX = 1 << 22;
+
+// items of the group's clouds from ipre (prefix of the per-cloud item
+// counts) and tpre (prefix of the per-cloud tile counts), one thread per item
+__global__ void exact_items_kernel(const int64_t* __restrict__ ipre, const int64_t* __restrict__ tpre, int nc,
+                                   uint64_t* __restrict__ items) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ipre[nc]) return;
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ipre[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t li = x - ipre[lo], nit = ipre[lo + 1] - ipre[lo], nt = tpre[lo + 1] - tpre[lo];
+  uint32_t low = EXACT_PRIM;
+  if (li < nit - 1) {
+    const int64_t s = li * EXACT_TPI;
+    low = (uint32_t)(s << EXACT_TPI_BITS) | (uint32_t)(min<int64_t>(EXACT_TPI, nt - s) - 1);
+  }
+  items[x] = ((uint64_t)(uint32_t)lo << 32) | low;
+}
+
+__global__ __launch_bounds__(PRIM_NT_DM) void exact_tree_kernel(
+    const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
+    const uint64_t* __restrict__ items, int64_t nitems, const int64_t* __restrict__ dmoff,
+    float* __restrict__ D, int* __restrict__ queue, int* __restrict__ done, int* __restrict__ err,
+    int32_t* __restrict__ ou, int32_t* __restrict__ ov, float* __restrict__ ow, float* __restrict__ W,
+    float* __restrict__ grad) {
+  constexpr int NT = PRIM_NT_DM, NGT = NT / PD_NT;   // tiles in flight per block
+  static_assert(NGT * 2 * PD_T * PD_LD <= 3 * FUSED_MAX, "tile buffers fit the Prim arrays");
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  int* endp = reinterpret_cast<int*>(smem);      // after Prim: list ends ...
+  int* kid = endp + FUSED_MAX;                   // ... and children lists
+  int* par = kid + FUSED_MAX;                    // tree parent of each vertex
+  __shared__ uint64_t wkeys[2 * NT / 64];
+  __shared__ float ss[NT], ee[NT];
+  __shared__ uint64_t item_s;
+  const int t = threadIdx.x, g = t / PD_NT;
+  float* As = reinterpret_cast<float*>(smem) + g * 2 * PD_T * PD_LD;
+  float* Bs = As + PD_T * PD_LD;
+  // Thread 0 alone talks to the queue and the counters, always right before
+  // a barrier of the whole block and never on a path that skips one: the
+  // count of a finished tile item is added when the next item is taken.
+  int pend_c = -1, pend_n = 0;
+  while (true) {
     if (t == 0) {
-      for (int c = 1; c < nb; ++c) endp[par[c]] += 1;
-      int run = 0;
-      for (int p = 0; p < nb; ++p) {
-        int cnt = endp[p];
-        endp[p] = run;
-        run += cnt;
-      }
-      for (int c = 1; c < nb; ++c) kid[endp[par[c]]++] = c;
+      if (pend_c >= 0) __hip_atomic_fetch_add(done + pend_c, pend_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const int idx = atomicAdd(queue, 1);
+      item_s = idx < nitems ? items[idx] : ~0ull;
     }
     __syncthreads();
-    // ---- gradient rows, one 16-lane group per row
-    for (int v = grp; v < nb; v += NG) {
-      const float* xv = X + (c0 + v) * d;
-      float* out = grad + (c0 + v) * d;
-      const int k0 = v == 0 ? 0 : endp[v - 1], k1 = endp[v];
-      for (int t0 = 0; t0 < d; t0 += 16 * 8) {
-        float acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.f;
-        for (int e = (v == 0 ? k0 : k0 - 1); e < k1; ++e) {
-          const int o = (e < k0) ? par[v] : kid[e];
-          const float* xo = X + (c0 + o) * d;
-          float s = sq32_group(xv, xo, d, r16);
-          if (s == 0.f) continue;
-          float w = __builtin_sqrtf(s);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            int tt = t0 + q * 16 + r16;
-            if (tt < d) acc[q] += (xv[tt] - xo[tt]) / w;
+    const uint64_t it = item_s;
+    __syncthreads();   // every thread has read item_s before it is rewritten
+    if (it == ~0ull) break;
+    const int cpos = (int)(it >> 32);
+    const uint32_t low = (uint32_t)it;
+    const int b = order[cpos];
+    const int64_t c0 = offs[b];
+    const int nb = (int)(offs[b + 1] - c0);
+    float* Dc = D + dmoff[b];
+    if (low != EXACT_PRIM) {
+      const int s0 = (int)(low >> EXACT_TPI_BITS), cnt = (int)(low & (EXACT_TPI - 1)) + 1;
+      for (int p = 0; p < cnt; p += NGT)
+        pair_tile(X, d, c0, nb, s0 + p + g, p + g < cnt, As, Bs, t & (PD_NT - 1), Dc);
+      // every wave's matrix stores have reached its XCD's L2 before the
+      // barrier (vmcnt(0)); thread 0's agent-scope release then writes that
+      // L2 back once per item, before the count is raised
+      __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
+      __syncthreads();
+      pend_c = cpos;
+      pend_n = cnt;
+    } else {
+      pend_c = -1;
+      if (t == 0) {
+        const int T = (nb + PD_T - 1) / PD_T, need = T * (T + 1) / 2;
+        int spins = 0;
+        while (__hip_atomic_load(done + cpos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins == EXACT_SPIN_MAX) {
+            atomicOr(err, 1);
+            break;
           }
         }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          int tt = t0 + q * 16 + r16;
-          if (tt < d) out[tt] = acc[q];
-        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        par[0] = -1;
       }
+      __syncthreads();
+      const int64_t eo = c0 - b;
+      auto emit = [&](int step, int p, int j, float w) {
+        par[j] = p;
+        ou[eo + step - 1] = (int32_t)(c0 + p);
+        ov[eo + step - 1] = (int32_t)(c0 + j);
+        ow[eo + step - 1] = w;
+      };
+      prim_cloud_dm<NT, FUSED_MAX / NT>(Dc, nb, wkeys, emit);
+      __threadfence_block();
+      __syncthreads();
+      cloud_tail<NT>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, ss, ee);
     }
-    __syncthreads();
   }
 }
 
@@ -1081,11 +1239,10 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   return FAMST_OK;
 }
 
-template <int NT, int MODE>
+template <int NT, bool VEC>
 static int launch_fused(dim3 grid, hipStream_t s, const float* X, int d, const int64_t* offs, const int* order, int nc,
-                        int* queue, int32_t* tu, int32_t* tv, float* tw, float* W, float* grad, const float* D,
-                        const int64_t* dmoff) {
-  auto kern = prim_fused_kernel<NT, MODE>;
+                        int* queue, int32_t* tu, int32_t* tv, float* tw, float* W, float* grad) {
+  auto kern = prim_fused_kernel<NT, VEC>;
   const size_t lds = (size_t)3 * FUSED_MAX * 4;
   static bool attr = false;
   if (!attr) {
@@ -1093,8 +1250,7 @@ static int launch_fused(dim3 grid, hipStream_t s, const float* X, int d, const i
                                   (int)lds));
     attr = true;
   }
-  return launch("dense_prim_fused", kern, grid, dim3(NT), lds, s, X, d, offs, order, nc, queue, tu, tv, tw, W, grad, D,
-                dmoff);
+  return launch("dense_prim_fused", kern, grid, dim3(NT), lds, s, X, d, offs, order, nc, queue, tu, tv, tw, W, grad);
 }
 
 extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const int64_t* offs_h,
@@ -1122,18 +1278,23 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   // all of them at once, and a smaller workspace that still holds the
   // largest cloud's matrix runs the clouds in consecutive groups that fit
   const bool dm = d <= DMAT_MAXD;
-  int64_t mtot = 0, mmax = 0;
+  int64_t mtot = 0, mmax = 0, itot = 0;
   for (int b = 0; b < B; ++b) {
-    const int64_t nb = offs[b + 1] - offs[b];
+    const int64_t nb = offs[b + 1] - offs[b], T = (nb + PD_T - 1) / PD_T;
     mtot += nb * nb;
     mmax = std::max(mmax, nb * nb);
+    itot += (T * (T + 1) / 2 + EXACT_TPI - 1) / EXACT_TPI + 1;
   }
   Carve cv(ws);
   int64_t* offs_d = cv.take<int64_t>(B + 1);
   int* order_d = cv.take<int>(B);
-  int* queue = cv.take<int>(1);
+  int* queue = cv.take<int>(2);   // queue, error flag
   int64_t* dmoff_d = cv.take<int64_t>(dm ? B : 0);
+  // per group: prefixes of the clouds' tile and item counts (B + groups + ... <= 2 B + 1 entries)
   int64_t* tpre_d = cv.take<int64_t>(dm ? 2 * B + 1 : 0);
+  int64_t* ipre_d = cv.take<int64_t>(dm ? 2 * B + 1 : 0);
+  int* done_d = cv.take<int>(dm ? B : 0);
+  uint64_t* items_d = cv.take<uint64_t>(dm ? itot : 0);
   const size_t fixed = cv.bytes();
   // the matrices, then FUSED_MAX zeros that the last Prim slots may read
   float* D = cv.take<float>(dm ? mtot + FUSED_MAX : 0);
@@ -1147,24 +1308,27 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   // groups of clouds (consecutive in the processing order) whose matrices fit
   const int64_t cap = dm ? (int64_t)((*ws_bytes - fixed) / 4) - FUSED_MAX : 0;
   std::vector<int> gstart{0};
-  std::vector<int64_t> dmoff(dm ? B : 0), tpre, gused;   // gused: matrix floats of each group
+  std::vector<int64_t> dmoff(dm ? B : 0), tpre, ipre, gused;   // gused: matrix floats of each group
   if (dm) {
-    int64_t used = 0, tiles = 0;
+    int64_t used = 0, tiles = 0, its = 0;
     tpre.push_back(0);
+    ipre.push_back(0);
     for (int i = 0; i < B; ++i) {
       const int b = order[i];
-      const int64_t nb = offs[b + 1] - offs[b], T = (nb + PD_T - 1) / PD_T;
+      const int64_t nb = offs[b + 1] - offs[b], T = (nb + PD_T - 1) / PD_T, nt = T * (T + 1) / 2;
       if (used + nb * nb > cap) {   // start a new group
         gstart.push_back(i);
         gused.push_back(used);
-        used = 0;
-        tiles = 0;
+        used = tiles = its = 0;
         tpre.push_back(0);
+        ipre.push_back(0);
       }
       dmoff[b] = used;
       used += nb * nb;
-      tiles += T * (T + 1) / 2;
+      tiles += nt;
+      its += (nt + EXACT_TPI - 1) / EXACT_TPI + 1;
       tpre.push_back(tiles);
+      ipre.push_back(its);
     }
     gused.push_back(used);
   }
@@ -1175,33 +1339,50 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   if (dm) {
     FAMST_HIP(hipMemcpyAsync(dmoff_d, dmoff.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
     FAMST_HIP(hipMemcpyAsync(tpre_d, tpre.data(), sizeof(int64_t) * tpre.size(), hipMemcpyHostToDevice, s));
+    FAMST_HIP(hipMemcpyAsync(ipre_d, ipre.data(), sizeof(int64_t) * ipre.size(), hipMemcpyHostToDevice, s));
   }
   FAMST_HIP(hipStreamSynchronize(s));  // host arrays copied before they go out of scope
   int dev = 0, ncu = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int mode = dm ? 2 : ((d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) ? 1 : 0);
+  FAMST_TRY(fill_i32(queue, 0, 2, s));
   for (size_t gi = 0; gi + 1 < gstart.size(); ++gi) {
     const int g0 = gstart[gi], nc = gstart[gi + 1] - g0;
     if (dm) {
-      // the group's prefix of tile counts sits at tpre[g0 + gi .. g0 + gi + nc]
-      const int64_t* tp = tpre_d + g0 + gi;
-      const int64_t ntile = tpre[g0 + gi + nc];
-      FAMST_TRY(launch("pair_matrix", pair_matrix_kernel, dim3(stride_grid(ntile)), dim3(PD_NT), 0, s, X, d,
-                       offs_d, order_d + g0, nc, tp, dmoff_d, D));
-      FAMST_HIP(hipMemsetAsync(D + gused[gi], 0, sizeof(float) * FUSED_MAX, s));
+      // the group's prefixes sit at [g0 + gi .. g0 + gi + nc]
+      const int64_t nit = ipre[g0 + gi + nc];
+      FAMST_TRY(fill_i32(reinterpret_cast<int32_t*>(D + gused[gi]), 0, FUSED_MAX, s));
+      FAMST_TRY(fill_i32(queue, 0, 1, s));
+      FAMST_TRY(fill_i32(done_d, 0, nc, s));
+      FAMST_TRY(launch("exact_items", exact_items_kernel, dim3(cdiv(nit, 256)), dim3(256), 0, s,
+                       ipre_d + g0 + gi, tpre_d + g0 + gi, nc, items_d));
+      static bool attr = false;
+      const size_t lds = (size_t)3 * FUSED_MAX * 4;
+      if (!attr) {
+        FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(exact_tree_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+      }
+      FAMST_TRY(launch("exact_tree", exact_tree_kernel, dim3((unsigned)std::min<int64_t>(nit, ncu)),
+                       dim3(PRIM_NT_DM), lds, s, X, d, offs_d, order_d + g0, items_d, nit, dmoff_d, D, queue,
+                       done_d, queue + 1, tu, tv, tw, W, grad_X));
+      continue;
     }
-    FAMST_HIP(hipMemsetAsync(queue, 0, sizeof(int), s));
+    FAMST_TRY(fill_i32(queue, 0, 1, s));
     const dim3 grid(std::min(nc, ncu));
-    if (mode == 2)
-      FAMST_TRY((launch_fused<PRIM_NT_DM, 2>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W,
-                                             grad_X, D, dmoff_d)));
-    else if (mode == 1)
-      FAMST_TRY((launch_fused<PRIM_NT, 1>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W, grad_X,
-                                          nullptr, nullptr)));
+    if ((d == 64) && (reinterpret_cast<uintptr_t>(X) % 16 == 0))
+      FAMST_TRY((launch_fused<PRIM_NT, true>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W,
+                                             grad_X)));
     else
-      FAMST_TRY((launch_fused<PRIM_NT, 0>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W, grad_X,
-                                          nullptr, nullptr)));
+      FAMST_TRY((launch_fused<PRIM_NT, false>(grid, s, X, d, offs_d, order_d + g0, nc, queue, tu, tv, tw, W,
+                                              grad_X)));
+  }
+  if (dm) {
+    // the bounded wait of a Prim item ran out: the outputs are not valid
+    int e = 0;
+    FAMST_HIP(hipMemcpyAsync(&e, queue + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipStreamSynchronize(s));
+    if (e) return FAMST_ETIMEOUT;
   }
   return FAMST_OK;
 }

@@ -58,7 +58,7 @@ def test_constants_match_header():
     L = _lib()
     txt = open(HEADER).read()
     for name in ["FAMST_OK", "FAMST_EINVAL", "FAMST_ECAPACITY", "FAMST_EDISCONNECTED", "FAMST_EHIP",
-                 "FAMST_ENOTIMPL", "FAMST_ENONFINITE", "FAMST_EWORKSPACE", "FAMST_WNOTCONVERGED",
+                 "FAMST_ENOTIMPL", "FAMST_ENONFINITE", "FAMST_EWORKSPACE", "FAMST_ETIMEOUT", "FAMST_WNOTCONVERGED",
                  "FAMST_FP32", "FAMST_BF16", "FAMST_FP8_E4M3", "FAMST_EXACT", "FAMST_BORUVKA",
                  "FAMST_KRUSKAL", "FAMST_DENSE_PRIM", "FAMST_NSTATS", "FAMST_NNDESCENT",
                  "FAMST_REFINE_MAX_ROUNDS"]:

@@ -169,6 +169,28 @@ def test_dense_fused_persistent_batch_matches_oracle():
     assert np.array_equal(G, G2)
 
 
+@pytest.mark.parametrize("d", [80, 128])
+def test_dense_fused_distances_on_the_fly_above_64_dims(d):
+    """d > 64 keeps no pair matrices: Prim computes each distance as it goes.
+    Weight and gradient per cloud against the oracle's float64 Prim, the same
+    tree as the unfused dense path, and the same bits on a second launch."""
+    X, offs = datagen.clouds(n_clouds=12, lo=30, hi=700, d=d, seed=d)
+    print(f"case dense fused on the fly d={d} sizes={np.diff(offs).tolist()}", flush=True)
+    Xd = _dev(X, torch.float32)
+    tu, tv, tw, W, G = (t.cpu().numpy() for t in F.mst_dense_fused(Xd, offs=offs))
+    for b in range(len(offs) - 1):
+        sl = slice(offs[b], offs[b + 1])
+        ref = oracle.prim_exact(X[sl])
+        assert math.isclose(float(W[b]), ref[3], rel_tol=1e-5)
+        e0, e1 = offs[b] - b, offs[b + 1] - b - 1
+        gref = oracle.mst_weight_grad(X[sl], tu[e0:e1] - offs[b], tv[e0:e1] - offs[b])
+        np.testing.assert_allclose(G[sl], gref, atol=1e-4)
+    a = F.mst(Xd, algo="prim", offs=offs)
+    assert sorted(zip(np.minimum(tu, tv).tolist(), np.maximum(tu, tv).tolist())) == \
+        sorted(zip(a[0].cpu().numpy().tolist(), a[1].cpu().numpy().tolist()))
+    assert np.array_equal(G, F.mst_dense_fused(Xd, offs=offs)[4].cpu().numpy())
+
+
 @pytest.mark.parametrize("d", [16, 64])
 def test_dense_fused_ties_and_duplicates_match_unfused_prim(d):
     """Exact ties everywhere: integer coordinates, duplicated rows and a cloud
