@@ -770,12 +770,26 @@ constexpr int FUSED_MAX = 12288;
 // id), and the gradient rows, one
 // 16-lane group per row: its parent edge first, then its children in
 // ascending id, so the result is deterministic.  endp and kid must not
-// overlap par.
-template <int NT>
+// overlap par.  IT: int, or uint16_t (ids below 2^16) to save LDS.  wv: the
+// weight of each vertex's parent edge as Prim emitted it (the square root
+// of the canonical squared distance), or null to recompute it per edge.
+template <class IT>
+__device__ __forceinline__ void lds_count_add(IT* a, int p) {
+  if constexpr (sizeof(IT) == 4) {
+    atomicAdd(reinterpret_cast<int*>(a) + p, 1);
+  } else {
+    // the 32-bit word holding a[p]; a count stays below 2^16, so the low
+    // half never carries into the high one
+    static_assert(sizeof(IT) == 2, "16- or 32-bit lists");
+    atomicAdd(reinterpret_cast<unsigned*>(a) + (p >> 1), (p & 1) ? 0x10000u : 1u);
+  }
+}
+
+template <int NT, class IT>
 __device__ void cloud_tail(const float* __restrict__ X, int d, int64_t c0, int nb, int64_t eo, int b,
                            const float* __restrict__ ow, float* __restrict__ W, float* __restrict__ grad,
-                           const int* __restrict__ par, int* __restrict__ endp, int* __restrict__ kid,
-                           float* __restrict__ ss, float* __restrict__ ee) {
+                           const IT* __restrict__ par, IT* __restrict__ endp, IT* __restrict__ kid,
+                           const float* __restrict__ wv, float* __restrict__ ss, float* __restrict__ ee) {
   const int t = threadIdx.x, grp = t >> 4, r16 = t & 15;
   constexpr int NG = NT / 16;
   // ---- tree weight, compensated, in insertion order
@@ -808,13 +822,13 @@ __device__ void cloud_tail(const float* __restrict__ X, int d, int64_t c0, int n
   // as the end of p's list
   for (int j = t; j < nb; j += NT) endp[j] = 0;
   __syncthreads();
-  for (int c = 1 + t; c < nb; c += NT) atomicAdd(&endp[par[c]], 1);
+  for (int c = 1 + t; c < nb; c += NT) lds_count_add(endp, (int)par[c]);
   __syncthreads();
   if (t < 64) {
     const int lane = t, per = (nb + 63) / 64;
     const int a = min(nb, lane * per), e = min(nb, a + per);
     int sum = 0;
-    for (int p = a; p < e; ++p) sum += endp[p];
+    for (int p = a; p < e; ++p) sum += (int)endp[p];
     int incl = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -823,53 +837,63 @@ __device__ void cloud_tail(const float* __restrict__ X, int d, int64_t c0, int n
     }
     int run = incl - sum;
     for (int p = a; p < e; ++p) {
-      const int cnt = endp[p];
-      endp[p] = run;
+      const int cnt = (int)endp[p];
+      endp[p] = (IT)run;
       run += cnt;
     }
     for (int base = 1; base < nb; base += 64) {
       const int c = base + lane;
       const bool act = c < nb;
-      const int P = act ? par[c] : -1;
+      const int P = act ? (int)par[c] : -1;
       uint64_t todo = __ballot(act);
       while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const int P0 = __shfl(P, leader);
         const uint64_t m = __ballot(act && P == P0);
-        const int start = endp[P0];
-        if (act && P == P0) kid[start + __popcll(m & ((1ull << lane) - 1))] = c;
-        if (lane == leader) endp[P0] = start + __popcll(m);
+        const int start = (int)endp[P0];
+        if (act && P == P0) kid[start + __popcll(m & ((1ull << lane) - 1))] = (IT)c;
+        if (lane == leader) endp[P0] = (IT)(start + __popcll(m));
         todo &= ~m;
       }
     }
   }
   __syncthreads();
-  // ---- gradient rows, one 16-lane group per row
+  // ---- gradient rows, one 16-lane group per row: lane r16 owns the
+  // dimensions 4 r16 .. 4 r16 + 3 of each 64 (the chunks of sq32_group);
+  // per dimension, (x_v - x_o) / w summed over the edges in list order
   for (int v = grp; v < nb; v += NG) {
     const float* xv = X + (c0 + v) * d;
     float* out = grad + (c0 + v) * d;
-    const int k0 = v == 0 ? 0 : endp[v - 1], k1 = endp[v];
-    for (int t0 = 0; t0 < d; t0 += 16 * 8) {
-      float acc[8];
+    const int k0 = v == 0 ? 0 : (int)endp[v - 1], k1 = (int)endp[v];
+    const int e0 = v == 0 ? k0 : k0 - 1;   // the parent edge first
+    auto other = [&](int e) { return e < k0 ? (int)par[v] : (int)kid[e]; };
+    for (int p0 = 0; p0 < d; p0 += 64) {   // every lane of the group takes every pass
+      const int t0 = p0 + 4 * r16;
+      float a4[4], v4[4];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = 0.f;
-      for (int e = (v == 0 ? k0 : k0 - 1); e < k1; ++e) {
-        const int o = (e < k0) ? par[v] : kid[e];
+      for (int q = 0; q < 4; ++q) {
+        a4[q] = 0.f;
+        v4[q] = t0 + q < d ? xv[t0 + q] : 0.f;
+      }
+      for (int e = e0; e < k1; ++e) {
+        const int o = other(e);
         const float* xo = X + (c0 + o) * d;
-        float s = sq32_group(xv, xo, d, r16);
-        if (s == 0.f) continue;
-        float w = __builtin_sqrtf(s);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          int tt = t0 + q * 16 + r16;
-          if (tt < d) acc[q] += (xv[tt] - xo[tt]) / w;
+        float w;
+        if (wv) {
+          w = wv[e < k0 ? v : o];
+        } else {
+          w = __builtin_sqrtf(sq32_group(xv, xo, d, r16));
         }
+        if (w == 0.f) continue;
+        float o4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o4[q] = t0 + q < d ? xo[t0 + q] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a4[q] += (v4[q] - o4[q]) / w;
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        int tt = t0 + q * 16 + r16;
-        if (tt < d) out[tt] = acc[q];
-      }
+      for (int q = 0; q < 4; ++q)
+        if (t0 + q < d) out[t0 + q] = a4[q];
     }
   }
   __syncthreads();
@@ -916,7 +940,7 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
     prim_cloud<NT, VEC, FUSED_MAX / NT>(X, d, c0, nb, keys, wkeys, &mcount, emit);
     __threadfence_block();
     __syncthreads();
-    cloud_tail<NT>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, ss, ee);
+    cloud_tail<NT, int>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, nullptr, ss, ee);
   }
 }
 
@@ -965,6 +989,8 @@ __global__ void exact_items_kernel(const int64_t* __restrict__ ipre, const int64
   items[x] = ((uint64_t)(uint32_t)lo << 32) | low;
 }
 
+constexpr size_t EXACT_LDS = (size_t)2 * PRIM_NT_DM / PD_NT * PD_T * PD_LD * sizeof(float);
+
 __global__ __launch_bounds__(PRIM_NT_DM) void exact_tree_kernel(
     const float* __restrict__ X, int d, const int64_t* __restrict__ offs, const int* __restrict__ order,
     const uint64_t* __restrict__ items, int64_t nitems, const int64_t* __restrict__ dmoff,
@@ -972,11 +998,14 @@ __global__ __launch_bounds__(PRIM_NT_DM) void exact_tree_kernel(
     int32_t* __restrict__ ou, int32_t* __restrict__ ov, float* __restrict__ ow, float* __restrict__ W,
     float* __restrict__ grad) {
   constexpr int NT = PRIM_NT_DM, NGT = NT / PD_NT;   // tiles in flight per block
-  static_assert(NGT * 2 * PD_T * PD_LD <= 3 * FUSED_MAX, "tile buffers fit the Prim arrays");
+  static_assert(NGT * 2 * PD_T * PD_LD * sizeof(float) <= EXACT_LDS, "tile buffers fit");
+  static_assert(FUSED_MAX * (3 * sizeof(uint16_t) + sizeof(float)) <= EXACT_LDS, "Prim arrays fit");
+  static_assert(FUSED_MAX <= 65536, "16-bit local ids");
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  int* endp = reinterpret_cast<int*>(smem);      // after Prim: list ends ...
-  int* kid = endp + FUSED_MAX;                   // ... and children lists
-  int* par = kid + FUSED_MAX;                    // tree parent of each vertex
+  float* wv = reinterpret_cast<float*>(smem);                    // weight of each vertex's parent edge
+  uint16_t* endp = reinterpret_cast<uint16_t*>(wv + FUSED_MAX);  // after Prim: list ends ...
+  uint16_t* kid = endp + FUSED_MAX;                              // ... and children lists
+  uint16_t* par = kid + FUSED_MAX;                               // tree parent of each vertex
   __shared__ uint64_t wkeys[2 * NT / 64];
   __shared__ float ss[NT], ee[NT];
   __shared__ uint64_t item_s;
@@ -1027,12 +1056,13 @@ __global__ __launch_bounds__(PRIM_NT_DM) void exact_tree_kernel(
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        par[0] = -1;
+        par[0] = 0xFFFF;
       }
       __syncthreads();
       const int64_t eo = c0 - b;
       auto emit = [&](int step, int p, int j, float w) {
-        par[j] = p;
+        par[j] = (uint16_t)p;
+        wv[j] = w;
         ou[eo + step - 1] = (int32_t)(c0 + p);
         ov[eo + step - 1] = (int32_t)(c0 + j);
         ow[eo + step - 1] = w;
@@ -1040,7 +1070,7 @@ __global__ __launch_bounds__(PRIM_NT_DM) void exact_tree_kernel(
       prim_cloud_dm<NT, FUSED_MAX / NT>(Dc, nb, wkeys, emit);
       __threadfence_block();
       __syncthreads();
-      cloud_tail<NT>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, ss, ee);
+      cloud_tail<NT, uint16_t>(X, d, c0, nb, eo, b, ow, W, grad, par, endp, kid, wv, ss, ee);
     }
   }
 }
@@ -1357,14 +1387,13 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
       FAMST_TRY(launch("exact_items", exact_items_kernel, dim3(cdiv(nit, 256)), dim3(256), 0, s,
                        ipre_d + g0 + gi, tpre_d + g0 + gi, nc, items_d));
       static bool attr = false;
-      const size_t lds = (size_t)3 * FUSED_MAX * 4;
       if (!attr) {
         FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(exact_tree_kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)EXACT_LDS));
         attr = true;
       }
       FAMST_TRY(launch("exact_tree", exact_tree_kernel, dim3((unsigned)std::min<int64_t>(nit, ncu)),
-                       dim3(PRIM_NT_DM), lds, s, X, d, offs_d, order_d + g0, items_d, nit, dmoff_d, D, queue,
+                       dim3(PRIM_NT_DM), EXACT_LDS, s, X, d, offs_d, order_d + g0, items_d, nit, dmoff_d, D, queue,
                        done_d, queue + 1, tu, tv, tw, W, grad_X));
       continue;
     }
