@@ -288,10 +288,12 @@ int famst_mst_backward_noalloc(const float* X, int64_t n, int32_t d,
  * first, then its children in ascending id, so G is deterministic.
  *   tu, tv, tw  out [n - B];  W out [B];  grad_X out [n][d] (unscaled G)
  * Every cloud must hold at most 12288 points (FAMST_ENOTIMPL otherwise).
- * Distances: for d <= 64 a first kernel stores the squared distance of every
- * pair of every cloud (the library's canonical float32 bits, nb^2 floats
- * per cloud in the workspace) and Prim reads one matrix row per step; for
- * d > 64 they are computed on the fly.  Both give the same tree.  The size
+ * Distances: for d <= 64 the same launch first stores the squared distance
+ * of every pair of a cloud (the library's canonical float32 bits, nb^2
+ * floats per cloud in the workspace, tiles spread over all blocks) and
+ * Prim then reads one matrix row per step; for d > 64 they are computed on
+ * the fly.  Both give the same tree.  FAMST_ETIMEOUT if a block waiting for
+ * a cloud's matrix gave up (a library fault; outputs invalid).  The size
  * query (ws == NULL) asks for all matrices at once; a workspace that holds
  * at least the fixed part plus the largest cloud's matrix is accepted too,
  * and the clouds then run in consecutive groups (largest first) whose
