@@ -287,7 +287,9 @@ int famst_mst_backward_noalloc(const float* X, int64_t n, int32_t d,
  * order as (tu, tv) = (parent, child); each row of G sums its parent edge
  * first, then its children in ascending id, so G is deterministic.
  *   tu, tv, tw  out [n - B];  W out [B];  grad_X out [n][d] (unscaled G)
- * Every cloud must hold at most 12288 points (FAMST_ENOTIMPL otherwise).
+ * Every cloud must hold at most 12288 points, and for d <= 64 the work
+ * items (per cloud: one per 64 tiles of 64 x 64 pairs, plus one) must number
+ * below 2^31 - 2^16 (FAMST_ENOTIMPL otherwise).
  * Distances: for d <= 64 the same launch first stores the squared distance
  * of every pair of a cloud (the library's canonical float32 bits, nb^2
  * floats per cloud in the workspace, tiles spread over all blocks) and

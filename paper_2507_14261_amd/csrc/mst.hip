@@ -1328,6 +1328,9 @@ extern "C" int famst_mst_dense_fused(const float* X, int64_t n, int32_t d, const
   const size_t fixed = cv.bytes();
   // the matrices, then FUSED_MAX zeros that the last Prim slots may read
   float* D = cv.take<float>(dm ? mtot + FUSED_MAX : 0);
+  // the queue hands out item indices from a 32-bit counter (each block takes
+  // one index past the end)
+  if (dm && itot > (int64_t)INT32_MAX - 65536) return FAMST_ENOTIMPL;
   if (!ws) {
     *ws_bytes = cv.bytes();
     return FAMST_OK;
