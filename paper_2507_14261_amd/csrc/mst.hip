@@ -177,6 +177,77 @@ __global__ void bv_relabel_kernel(int32_t* __restrict__ comp, const int32_t* __r
   comp[v] = P[comp[v]];
 }
 
+// Boruvka for small inputs: every round in one block, with the minimum keys,
+// the component labels and the parents in LDS (8 + 2 + 2 bytes per vertex),
+// so a call needs no host round trip per round.  Same keys and the same hook
+// rule as the kernels above, so the same tree.  Each round scans all m
+// edges (an edge inside one component is skipped); the edge count is read
+// on the device.
+constexpr int BV1_NT = 1024;
+constexpr int BV1_MAXN = 13312;           // 12 bytes of LDS per vertex
+constexpr int64_t BV1_MAXM = 1 << 18;     // edges scanned per round at most
+__global__ __launch_bounds__(BV1_NT) void bv_block_kernel(const int32_t* __restrict__ elo,
+                                                         const int32_t* __restrict__ ehi,
+                                                         const uint32_t* __restrict__ ewb,
+                                                         const int64_t* __restrict__ mptr, int n,
+                                                         uint8_t* __restrict__ in_tree) {
+  extern __shared__ __attribute__((aligned(16))) unsigned long long bsm[];
+  unsigned long long* best = bsm;                               // [n]
+  uint16_t* comp = reinterpret_cast<uint16_t*>(best + n);       // [n]
+  volatile uint16_t* P = comp + n;                              // [n], roots only
+  __shared__ int hooked_s;
+  const int t = threadIdx.x;
+  const int64_t m = *mptr;
+  for (int v = t; v < n; v += BV1_NT) comp[v] = (uint16_t)v;
+  for (int round = 0; round < 64; ++round) {
+    for (int v = t; v < n; v += BV1_NT) best[v] = ~0ull;
+    if (t == 0) hooked_s = 0;
+    __syncthreads();
+    for (int64_t e = t; e < m; e += BV1_NT) {
+      const int cu = comp[elo[e]], cv = comp[ehi[e]];
+      if (cu != cv) {
+        const unsigned long long key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
+        atomicMin(&best[cu], key);
+        atomicMin(&best[cv], key);
+      }
+    }
+    __syncthreads();
+    for (int c = t; c < n; c += BV1_NT) {
+      if (comp[c] != c) continue;
+      const unsigned long long key = best[c];
+      if (key == ~0ull) {
+        P[c] = (uint16_t)c;
+        continue;
+      }
+      const uint32_t e = (uint32_t)key;
+      const int cl = comp[elo[e]], ch = comp[ehi[e]];
+      const int other = cl == c ? ch : cl;
+      if (best[other] == key && c < other) {
+        P[c] = (uint16_t)c;   // the smaller root of a mutual pair stays
+      } else {
+        P[c] = (uint16_t)other;
+        in_tree[e] = 1;
+        hooked_s = 1;
+      }
+    }
+    __syncthreads();
+    if (!hooked_s) break;   // every thread reads it before the next round resets it
+    // pointer jumping: parents only move to their own parents' parents, and
+    // every chain ends at a root that stays, so each loop ends
+    for (int c = t; c < n; c += BV1_NT) {
+      if (comp[c] != c) continue;
+      while (true) {
+        const int p = P[c], pp = P[p];
+        if (p == pp) break;
+        P[c] = (uint16_t)pp;
+      }
+    }
+    __syncthreads();
+    for (int v = t; v < n; v += BV1_NT) comp[v] = P[comp[v]];
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- Kruskal
 __global__ void kr_keys_kernel(const uint32_t* __restrict__ ewb, int64_t m, uint64_t* __restrict__ keys) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1169,7 +1240,7 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
   int32_t* elo = cv.take<int32_t>(m0);
   int32_t* ehi = cv.take<int32_t>(m0);
   uint32_t* ewb = cv.take<uint32_t>(m0);
-  uint8_t* in_tree = cv.take<uint8_t>(m0);
+  uint8_t* in_tree = cv.take<uint8_t>((m0 + 3) / 4 * 4);   // whole 32-bit words (cleared as such)
   uint32_t* liveA = cv.take<uint32_t>(m0);
   uint32_t* liveB = cv.take<uint32_t>(m0);
   int32_t* comp = cv.take<int32_t>(n);
@@ -1204,6 +1275,34 @@ extern "C" int famst_mst(const float* X, int64_t n, int32_t d, const int64_t* of
                    svals, flag, pos, m0, elo, ehi, ewb));
   int64_t m = 0;
   int hbad = 0;
+  if (algo == FAMST_BORUVKA && n <= BV1_MAXN && m0 <= BV1_MAXM) {
+    // small input: all rounds in one block; the edge count stays on the
+    // device (the kernels below run over all m0 slots, zero past m), and
+    // invalid edges are reported after the tree
+    FAMST_TRY(fill_i32(reinterpret_cast<int32_t*>(in_tree), 0, (size_t)(m0 + 3) / 4, s));
+    static bool attr = false;
+    const size_t lds = (size_t)BV1_MAXN * 12;
+    if (!attr) {
+      FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bv_block_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      attr = true;
+    }
+    FAMST_TRY(launch("boruvka_block", bv_block_kernel, dim3(1), dim3(BV1_NT), (size_t)n * 12, s, elo, ehi, ewb,
+                     pos + m0, (int)n, in_tree));
+    FAMST_TRY(launch("tree_flags", u8_to_i64_kernel, dim3(cdiv(m0 + 1, 256)), dim3(256), 0, s, in_tree, m0,
+                     flag));
+    FAMST_TRY(exclusive_scan_i64(tmp, tmpb, flag, pos, m0 + 1, s));
+    int64_t cnt = 0;
+    FAMST_HIP(hipMemcpyAsync(&cnt, pos + m0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FAMST_HIP(hipStreamSynchronize(s));
+    if (hbad) return FAMST_EINVAL;
+    if (cnt != nt) return FAMST_EDISCONNECTED;
+    FAMST_TRY(launch("tree_compact", tree_compact_kernel, dim3(cdiv(m0, 256)), dim3(256), 0, s, in_tree,
+                     pos, m0, elo, ehi, ewb, tu, tv, tw));
+    FAMST_TRY(launch("tree_weight", tree_weight_kernel, dim3(B), dim3(256), 0, s, tw, offs_d, W));
+    return FAMST_OK;
+  }
   FAMST_HIP(hipMemcpyAsync(&m, pos + m0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
