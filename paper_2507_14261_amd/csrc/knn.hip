@@ -1345,8 +1345,20 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   if (!X || !nbr || !dist) return FAMST_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  // block descriptors and offsets (host -> device)
-  BlockDesc* hd = new BlockDesc[nblk];
+  // block descriptors and offsets (host -> device); the host copy lives
+  // until the stream has passed the synchronisation after the non-finite
+  // check below (or until any earlier return, which synchronises first)
+  struct HostDesc {
+    BlockDesc* p;
+    hipStream_t s;
+    ~HostDesc() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        delete[] p;
+      }
+    }
+  } hdesc{new BlockDesc[nblk], s};
+  BlockDesc* hd = hdesc.p;
   int bi = 0;
   for (int b = 0; b < B; ++b)
     for (int64_t q0 = offs[b]; q0 < offs[b + 1]; q0 += p.qblk)
@@ -1362,9 +1374,7 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   hipError_t e9 = sn ? hipMemsetAsync(Xp + sn * p.DP * esz, 0, (size_t)PADR * p.DP * esz, s) : hipSuccess;
   hipError_t e10 = sn ? hipMemsetAsync(nqp + sn, 0, PADR * sizeof(float), s) : hipSuccess;
   hipError_t e12 = f8sp ? hipMemsetAsync(sclp + sn, 0, PADR * sizeof(float), s) : hipSuccess;
-  hipError_t e5 = hipStreamSynchronize(s);  // host descriptor copy complete before free
-  delete[] hd;
-  if (e1 || e2 || e3 || e4 || e5 || e6 || e7 || e8 || e9 || e10 || e11 || e12) return FAMST_EHIP;
+  if (e1 || e2 || e3 || e4 || e6 || e7 || e8 || e9 || e10 || e11 || e12) return FAMST_EHIP;
 
   const dim3 pgrid(std::min<unsigned>(cdiv(n, 4), 4096));
   if (prec == FAMST_FP32)
@@ -1379,6 +1389,8 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   unsigned bad_flag = 0;
   FAMST_HIP(hipMemcpyAsync(&bad_flag, gstat, 4, hipMemcpyDeviceToHost, s));
   FAMST_HIP(hipStreamSynchronize(s));
+  delete[] hdesc.p;   // its copy has completed
+  hdesc.p = nullptr;
   if (bad_flag) return FAMST_ENONFINITE;
 
   // matrix-core dot products and norms: |err| <= (2d + 8) 2^-24 (|x|^2 + |y|^2)

@@ -206,9 +206,11 @@ __global__ __launch_bounds__(BV1_NT) void bv_block_kernel(const int32_t* __restr
     for (int64_t e = t; e < m; e += BV1_NT) {
       const int cu = comp[elo[e]], cv = comp[ehi[e]];
       if (cu != cv) {
+        // a read first: late rounds send most edges to a few components, and
+        // atomics on one LDS word run one lane at a time
         const unsigned long long key = ((unsigned long long)ewb[e] << 32) | (unsigned long long)e;
-        atomicMin(&best[cu], key);
-        atomicMin(&best[cv], key);
+        if (key < best[cu]) atomicMin(&best[cu], key);
+        if (key < best[cv]) atomicMin(&best[cv], key);
       }
     }
     __syncthreads();
