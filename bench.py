@@ -55,7 +55,7 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 1.704, "write_GB": 0.512,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("exact_tree", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "776d2e522f740d6c23a745f2fd5ce6a201bac86d",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "26beb9da2b839ac108b2307e05a3402faf1a6606",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 40.507, "write_GB": 28.550,
         "profile": "profiles/exact_tree_clouds-256-d64_kernel_stats_and_hbm.md"},

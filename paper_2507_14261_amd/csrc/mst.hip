@@ -1030,9 +1030,9 @@ __global__ __launch_bounds__(NT) void prim_fused_kernel(
 // write-back, costly enough that one per wave per item doubled the launch)
 // with the count; the Prim side reads the count and takes an agent-scope
 // acquire before its rows, so matrix rows written on another XCD are seen
-// (without the pair the trees come out wrong).  No path of the item loop leaves thread 0 out of a barrier
-// (a `continue` after its divergent update let the compiler send the other
-// threads round the loop without it).
+// (without the pair the trees come out wrong).  No path of the item loop
+// leaves thread 0 out of a barrier (a `continue` after its divergent update
+// let the compiler send the other threads round the loop without it).
 // Item (64 bits): cloud position << 32 | low; low == EXACT_PRIM: the Prim
 // item; else tiles s .. s + c of the cloud, low = s << EXACT_TPI_BITS | c.
 constexpr uint32_t EXACT_PRIM = 0x80000000u;
