@@ -39,13 +39,13 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 968.465, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("rerank", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "d362bf9469f0a8ce0b8bc21f64dbf23923f2542a",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "860b25c13204c0c97e9571cd3adaeef3ecb8ffd6",
                     "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5.268, "write_GB": 0.256,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("prep", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "d362bf9469f0a8ce0b8bc21f64dbf23923f2542a",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "860b25c13204c0c97e9571cd3adaeef3ecb8ffd6",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 0.512, "write_GB": 0.272,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},

@@ -2,6 +2,8 @@
 // matrix-core distance screening with a fused per-row top-k', float32
 // direct-difference re-ranking and exact recomputation of rows the
 // screening bound cannot certify.
+#include <numeric>
+
 #include "famst_common.hpp"
 #include "prims.hpp"
 #include "select.hpp"
@@ -1360,7 +1362,13 @@ extern "C" int famst_knn_graph(const float* X, int64_t n, int32_t d, const int64
   } hdesc{new BlockDesc[nblk], s};
   BlockDesc* hd = hdesc.p;
   int bi = 0;
-  for (int b = 0; b < B; ++b)
+  // blocks of the largest clouds first: a block's work grows with its
+  // cloud's size, so late large clouds would leave a tail (ties by index)
+  std::vector<int> corder(B);
+  std::iota(corder.begin(), corder.end(), 0);
+  std::stable_sort(corder.begin(), corder.end(),
+                   [&](int a, int b) { return offs[a + 1] - offs[a] > offs[b + 1] - offs[b]; });
+  for (int b : corder)
     for (int64_t q0 = offs[b]; q0 < offs[b + 1]; q0 += p.qblk)
       hd[bi++] = BlockDesc{(int)q0, (int)offs[b + 1], (int)offs[b], (int)offs[b + 1]};
   hipError_t e1 = hipMemcpyAsync(desc, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s);
