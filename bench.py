@@ -54,6 +54,18 @@ MEASURED_TRAFFIC = {
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 1.704, "write_GB": 0.512,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
+    ("dist_topk", "lowrank-500k-d960"): {
+        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "e8f4edaaaa9d978f1854ca9bbedf002c9b849509",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 2770.8, "write_GB": 0.130,
+        "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
+    ("dist_topk", "vmf-4m-d96"): {
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "560a8ce67fbfe05e91620fa531c8fe584433e953",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+                    "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
+        "fetch_GB": 5785.4, "write_GB": 1.152,
+        "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("exact_tree", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "26beb9da2b839ac108b2307e05a3402faf1a6606",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
