@@ -51,6 +51,7 @@ def test_host_only_calls():
     lib = L.load()
     assert lib.famst_version() >= 100
     assert lib.famst_strerror(-3) == b"edges do not span every cloud"
+    assert lib.famst_strerror(-8) == b"a bounded wait inside a kernel ran out"
     assert lib.famst_strerror(0) == b"ok"
 
 
