@@ -443,6 +443,51 @@ __device__ __forceinline__ uint64_t prim_key(float w, int p, int j) {
          (uint64_t)(j < p);
 }
 constexpr uint64_t PRIM_DEAD = ~0ull;
+
+// The same minima, first over the 32 weight bits of the keys (bits 29..60;
+// a dead key's top word is all ones), with the 64-bit minimum only among
+// the lanes that tie on the weight: the same key in about half the
+// instructions when the minimum weight is unique.  wave_min_key: all 64
+// lanes; row_min_key: lanes 0..15.  Every lane returns the key.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ uint32_t dpp_min_step32(uint32_t v) {
+  const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+  return o < v ? o : v;
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_min_key(uint64_t v) {
+  const uint32_t w = (uint32_t)(v >> 29);
+  uint32_t m = w;
+  m = dpp_min_step32<0x111, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x112, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x113, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x114, 0xF, 0xE>(m);
+  m = dpp_min_step32<0x118, 0xF, 0xC>(m);
+  m = dpp_min_step32<0x142, 0xA, 0xF>(m);
+  m = dpp_min_step32<0x143, 0xC, 0xF>(m);
+  m = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+  const uint64_t tie = __ballot(w == m);
+  if (__popcll(tie) == 1) return readlane_u64(v, __builtin_ctzll(tie));
+  return wave_min_u64(w == m ? v : PRIM_DEAD);
+}
+__device__ __forceinline__ uint64_t row_min_key(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t w = lane < 16 ? (uint32_t)(v >> 29) : 0xFFFFFFFFu;
+  uint32_t m = w;
+  m = dpp_min_step32<0x111, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x112, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x113, 0xF, 0xF>(m);
+  m = dpp_min_step32<0x114, 0xF, 0xE>(m);
+  m = dpp_min_step32<0x118, 0xF, 0xC>(m);
+  m = (uint32_t)__builtin_amdgcn_readlane((int)m, 15);
+  const uint64_t tie = __ballot(lane < 16 && w == m);
+  if (__popcll(tie) == 1) return readlane_u64(v, __builtin_ctzll(tie));
+  return readlane_u64(row16_min_u64(lane < 16 && w == m ? v : PRIM_DEAD), 15);
+}
 __device__ __forceinline__ float key_w(uint64_t k) { return __uint_as_float((uint32_t)(k >> 29)); }
 __device__ __forceinline__ int key_j(uint64_t k) {
   return (k & 1) ? (int)((k >> 15) & 0x3FFF) : (int)((k >> 1) & 0x3FFF);
@@ -655,17 +700,12 @@ __device__ void prim_cloud_dm(const float* __restrict__ Dc, int nb, uint64_t* __
         }
       }
     }
-    const uint64_t wb = wave_min_u64(best);
+    const uint64_t wb = wave_min_key(best);
     uint64_t* wk = wkeys + (step & 1) * NW;
     if (lane == 0) wk[wave] = wb;
     __syncthreads();
     // the NW wave minima: lane l of each wave takes minimum l mod 16 (NW <= 16)
-    const uint64_t gb = [&] {
-      const uint64_t m = row16_min_u64((lane & 15) < NW ? wk[lane & 15] : PRIM_DEAD);
-      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m, 15);
-      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), 15);
-      return ((uint64_t)hi << 32) | lo;
-    }();
+    const uint64_t gb = row_min_key((lane & 15) < NW ? wk[lane & 15] : PRIM_DEAD);
     const int j = key_j(gb), p = key_p(gb);
     if (t == 0) emit(step, p, j, key_w(gb));
     jq = j - 1;
