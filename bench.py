@@ -67,9 +67,9 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 5785.4, "write_GB": 1.152,
         "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("exact_tree", "clouds-256-d64"): {
-        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "26beb9da2b839ac108b2307e05a3402faf1a6606",
+        "sources": {"paper_2507_14261_amd/csrc/mst.hip": "2dde04c5ee757ec24b70d6ac123096784b61d10f",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 40.507, "write_GB": 28.550,
+        "fetch_GB": 40.701, "write_GB": 28.549,
         "profile": "profiles/exact_tree_clouds-256-d64_kernel_stats_and_hbm.md"},
 }
 
