@@ -1153,8 +1153,9 @@ static int launch_hd(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, 
   auto kern = dist_topk_hd_kernel<PREC, SH>;
   static bool attr = false;
   if (!attr) {
+    // the exact ring size: the kernel's static merge scratch shares the CU's LDS
     FAMST_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)hd_lds_bytes<SH>()));
     attr = true;
   }
   return launch("dist_topk", kern, dim3(nblk), dim3(64 * HdShape<SH>::NW), hd_lds_bytes<SH>(), s, Xq, nq,

@@ -70,6 +70,11 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
   using LJ = typename ListRegs<QW>::J;
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
+  // the first tile's merges: float8 only (its wide band lets most of the
+  // first tile's rows pass; in bf16 the extra registers cost more than the
+  // merges save), and the four-wave shape has no LDS to spare
+  constexpr bool HD_MERGE = SH == 8 && F8;
+  __shared__ __attribute__((aligned(16))) float mscratch[HD_MERGE ? NW : 1][INIT_LDS_FLOATS];
 
   const BlockDesc bd = desc[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -157,7 +162,10 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
   for (int i = 0; i < HD_PIPE - 1; ++i) issue(i);
   const int nst = ntile * nks;
   int cs = 0, ct = tstart, ck = 0;   // stage slot, tile and K-step being computed
-  for (int st = 0; st < nst; ++st) {
+  // one stage: its products and, where it completes a tile, the tile's
+  // filter and list updates (MERGE: whole-block merges, for the scan's first
+  // tile; single insertions otherwise)
+  auto stage_step = [&](auto merge) __attribute__((always_inline)) {
     wait_vmcnt<(HD_PIPE - 2) * NLD>();   // this thread's loads of stage st are done
     __builtin_amdgcn_s_barrier();        // ... and every thread's; stage st-1 is consumed
     issue(cs == 0 ? HD_PIPE - 1 : cs - 1);   // into the slot stage st-1 used
@@ -244,15 +252,26 @@ __global__ __launch_bounds__(64 * HdShape<SH>::NW, 8 / HdShape<SH>::NW) void dis
           for (int e = 1; e < 8; ++e) m = fmaxf(m, acc[qb][2 * h + (e >> 2)][e & 3]);
           qbmask |= ballot(m >= -0.5f * U[qb]) ? (1u << qb) : 0u;
         }
-        if (qbmask)
-          insert_regs<QB, 8, true>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0, lane,
-                                   g, i16);
+        if (qbmask) {
+          if constexpr (decltype(merge)::value)
+            merge_regs<QB, 8, true>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0,
+                                    lane, g, i16, mscratch[wave]);
+          else
+            insert_regs<QB, 8, true>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0 + 32 * h, bd.c1, wq0,
+                                     lane, g, i16);
+        }
       }
       ck = 0;
       ct = ct + 1 == ntile ? 0 : ct + 1;
     }
     cs = cs + 1 == HD_PIPE ? 0 : cs + 1;
+  };
+  int st = 0;
+  if constexpr (HD_MERGE) {
+    const int nfirst = min(nst, nks);   // the stages of the first tile
+    for (; st < nfirst; ++st) stage_step(std::true_type{});
   }
+  for (; st < nst; ++st) stage_step(std::false_type{});
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 
   float nqv[QB];

@@ -84,6 +84,142 @@ struct Band {
   }
 };
 
+// ------------------------------------------- lists from the first rows
+// Per-wave LDS scratch of init_lists and merge_block: a 16 x 32 matrix
+// (query of a block, row of the 32-row group), the 16 queries' k-th entries
+// and their last entries.
+constexpr int INIT_LDS_FLOATS = 16 * 32 + 32;
+
+// Compare-exchange of (s, j) with the lane at distance M of the same
+// half-wave: where `asc`, the lower lane of the pair keeps the smaller key.
+template <int M>
+__device__ __forceinline__ void cex32(float& s, int& j, bool asc, int rel) {
+  const float ps = __shfl_xor(s, M);
+  const int pj = __shfl_xor(j, M);
+  const bool lower = (rel & M) == 0;
+  const bool pless = (ps < s) | ((ps == s) & (pj < j));
+  const bool sless = (s < ps) | ((s == ps) & (j < pj));
+  const bool take = (lower == asc) ? pless : sless;
+  s = take ? ps : s;
+  j = take ? pj : j;
+}
+
+// Bitonic sort of the 32 (s, j) of each half-wave into ascending (DESC:
+// descending) order.
+template <bool DESC = false>
+__device__ __forceinline__ void sort32(float& s, int& j, int rel) {
+#pragma unroll
+  for (int k = 2; k <= 32; k <<= 1) {
+    const bool asc = ((rel & k) == 0) != DESC;
+    if (k >= 32) cex32<16>(s, j, asc, rel);
+    if (k >= 16) cex32<8>(s, j, asc, rel);
+    if (k >= 8) cex32<4>(s, j, asc, rel);
+    if (k >= 4) cex32<2>(s, j, asc, rel);
+    cex32<1>(s, j, asc, rel);
+  }
+}
+__device__ __forceinline__ void sort32_asc(float& s, int& j, int rel) { sort32<false>(s, j, rel); }
+
+// The lists of a wave's queries built from the first 32 rows of the scan at
+// once: the first rows of a query all pass an empty list's filter, so
+// instead of 32 single insertions per query, each lane writes its 8 values
+// of query block qb (+inf where j is the query itself or past the cloud)
+// into a 16 x 32 (query, row) matrix, register pair L = 8 qb + c reads the
+// rows of its two queries (2c + half) and sorts them by (s, j), and the
+// thresholds follow from the new k-th entries.  The lists are then the 32
+// smallest (s, j) of those rows, as the single insertions would leave them.
+template <int QB, class LS, class LJ, class SpFn>
+__device__ __forceinline__ void init_lists(LS& ls, LJ& lj, float (&U)[QB], float nql, float bcl0, float bcl1,
+                                           const Band& band, int kk, SpFn spf, int t0, int c1, int wq0, int lane,
+                                           int g, int i16, float* mlds) {
+  const int half = lane >> 5, rel = lane & 31;
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = wq0 + qb * 16 + i16;
+    const float nqq = __shfl(nql, qb * 16 + i16);   // |x_q|^2 of the lane's query
+    const bool live = U[qb] != -F_INF;                // queries past the block stay empty
+    f32x4 w[2];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
+      w[e >> 2][e & 3] = (live & (j < c1) & (j != q)) ? spf(qb, e) + nqq : F_INF;
+    }
+    *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 4 * g) = w[0];
+    *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 16 + 4 * g) = w[1];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      float cs = mlds[(2 * c + half) * 32 + rel];
+      int cj = cs < F_INF ? t0 + rel : 0x7FFFFFFF;
+      sort32_asc(cs, cj, rel);
+      ls[qb * 8 + c] = cs;
+      lj[qb * 8 + c] = cj;
+      if (rel == kk - 1) mlds[512 + 2 * c + half] = cs;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const float Tk = mlds[512 + i16];
+    const float Un = (Tk - nqq) + band(Tk, __shfl(bcl0, qb * 16 + i16), __shfl(bcl1, qb * 16 + i16));
+    U[qb] = live ? Un : U[qb];
+    __builtin_amdgcn_wave_barrier();   // the scratch is rewritten for the next block
+  }
+}
+
+// A whole 32-row group merged into the lists of one query block at once:
+// where many elements of the block pass the filter (early in the scan, when
+// the lists are still far from final), one sort and one merge per register
+// pair replace the one-at-a-time insertions.  Each lane writes its passing
+// values (+inf elsewhere) into the per-wave 16 x 32 (query, row) matrix;
+// register pair L = 8 qb + c reads the rows of its two queries, sorts them
+// descending, and keeps the 32 smallest of them and its list (the pairwise
+// minimum of an ascending and a descending sequence is bitonic: five more
+// compare-exchange steps sort it).  The lists then hold the 32 smallest
+// (s, j) of their old entries and the passing elements; the thresholds
+// follow from the new k-th entries and never increase.  Elements the
+// one-at-a-time rule would have skipped once its threshold tightened can
+// stay in the list's tail; they only widen what the re-rank sees.
+template <bool CAPK, int NE, class LS, class LJ>
+__device__ __forceinline__ void merge_block(LS& ls, LJ& lj, float& Uq, int qb, const float (&sp)[NE],
+                                            const bool (&ok)[NE], float nql, float bcl0, float bcl1,
+                                            const Band& band, int kk, int t0, int lane, int g, int i16,
+                                            float* mlds) {
+  static_assert(NE == 8, "a 32-row group: eight elements per lane");
+  const int half = lane >> 5, rel = lane & 31;
+  const float nqq = __shfl(nql, qb * 16 + i16);   // |x_q|^2 of the lane's query
+  f32x4 w[2];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) w[e >> 2][e & 3] = ok[e] ? sp[e] + nqq : F_INF;
+  *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 4 * g) = w[0];
+  *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 16 + 4 * g) = w[1];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll 1   // one register pair at a time: the merge runs beside the next group's products
+  for (int c = 0; c < 8; ++c) {
+    float cs = mlds[(2 * c + half) * 32 + rel];
+    int cj = cs < F_INF ? t0 + rel : 0x7FFFFFFF;
+    sort32<true>(cs, cj, rel);
+    const int L = qb * 8 + c;
+    const float os = ls[L];
+    const int oj = lj[L];
+    const bool cl = (cs < os) | ((cs == os) & (cj < oj));
+    float ms = cl ? cs : os;
+    int mj = cl ? cj : oj;
+    cex32<16>(ms, mj, true, rel);
+    cex32<8>(ms, mj, true, rel);
+    cex32<4>(ms, mj, true, rel);
+    cex32<2>(ms, mj, true, rel);
+    cex32<1>(ms, mj, true, rel);
+    ls[L] = ms;
+    lj[L] = mj;
+    if (rel == kk - 1) mlds[512 + 2 * c + half] = ms;
+    if (CAPK && rel == 31) mlds[528 + 2 * c + half] = ms;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const float Tk = mlds[512 + i16];
+  float Un = (Tk - nqq) + band(Tk, __shfl(bcl0, qb * 16 + i16), __shfl(bcl1, qb * 16 + i16));
+  if constexpr (CAPK) Un = fminf(Un, mlds[528 + i16] - nqq);
+  Uq = Uq != -F_INF ? Un : Uq;   // queries past the block stay empty
+  __builtin_amdgcn_wave_barrier();   // the scratch is rewritten for the next block
+}
+
 // The filter threshold of a query is U = T_k - |x_q|^2 + band(T_k) with T_k
 // the k-th entry of its list (not the last): an element screened above it
 // cannot be among the k nearest, and U + |x_q|^2 at the end bounds every
@@ -155,79 +291,25 @@ __device__ __forceinline__ void insert_regs(LS& ls, LJ& lj, unsigned qbmask, flo
   }
 }
 
-// ------------------------------------------- lists from the first rows
-// Per-wave LDS scratch of init_lists: a 16 x 32 matrix (query of a block,
-// row of the 32-row group) and the 16 queries' k-th entries.
-constexpr int INIT_LDS_FLOATS = 16 * 32 + 16;
-
-// Compare-exchange of (s, j) with the lane at distance M of the same
-// half-wave: where `asc`, the lower lane of the pair keeps the smaller key.
-template <int M>
-__device__ __forceinline__ void cex32(float& s, int& j, bool asc, int rel) {
-  const float ps = __shfl_xor(s, M);
-  const int pj = __shfl_xor(j, M);
-  const bool lower = (rel & M) == 0;
-  const bool pless = (ps < s) | ((ps == s) & (pj < j));
-  const bool sless = (s < ps) | ((s == ps) & (j < pj));
-  const bool take = (lower == asc) ? pless : sless;
-  s = take ? ps : s;
-  j = take ? pj : j;
-}
-
-// Bitonic sort of the 32 (s, j) of each half-wave into ascending order.
-__device__ __forceinline__ void sort32_asc(float& s, int& j, int rel) {
-#pragma unroll
-  for (int k = 2; k <= 32; k <<= 1) {
-    const bool asc = (rel & k) == 0;
-    if (k >= 32) cex32<16>(s, j, asc, rel);
-    if (k >= 16) cex32<8>(s, j, asc, rel);
-    if (k >= 8) cex32<4>(s, j, asc, rel);
-    if (k >= 4) cex32<2>(s, j, asc, rel);
-    cex32<1>(s, j, asc, rel);
-  }
-}
-
-// The lists of a wave's queries built from the first 32 rows of the scan at
-// once: the first rows of a query all pass an empty list's filter, so
-// instead of 32 single insertions per query, each lane writes its 8 values
-// of query block qb (+inf where j is the query itself or past the cloud)
-// into a 16 x 32 (query, row) matrix, register pair L = 8 qb + c reads the
-// rows of its two queries (2c + half) and sorts them by (s, j), and the
-// thresholds follow from the new k-th entries.  The lists are then the 32
-// smallest (s, j) of those rows, as the single insertions would leave them.
-template <int QB, class LS, class LJ, class SpFn>
-__device__ __forceinline__ void init_lists(LS& ls, LJ& lj, float (&U)[QB], float nql, float bcl0, float bcl1,
-                                           const Band& band, int kk, SpFn spf, int t0, int c1, int wq0, int lane,
-                                           int g, int i16, float* mlds) {
-  const int half = lane >> 5, rel = lane & 31;
+// The update of merge_block for every query block with a passing element:
+// the form for the first groups of a scan, where most rows still pass.
+template <int QB, int NE, bool CAPK = false, class LS, class LJ, class SpFn>
+__device__ __forceinline__ void merge_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB], float nql,
+                                           float bcl0, float bcl1, const Band& band, int kk, SpFn spf, int t0,
+                                           int c1, int wq0, int lane, int g, int i16, float* mlds) {
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
+    if (!(qbmask & (1u << qb))) continue;
     const int q = wq0 + qb * 16 + i16;
-    const float nqq = __shfl(nql, qb * 16 + i16);   // |x_q|^2 of the lane's query
-    const bool live = U[qb] != -F_INF;                // queries past the block stay empty
-    f32x4 w[2];
+    float sp[NE];
+    bool ok[NE];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < NE; ++e) {
+      sp[e] = spf(qb, e);
       const int j = t0 + (e >> 2) * 16 + 4 * g + (e & 3);
-      w[e >> 2][e & 3] = (live & (j < c1) & (j != q)) ? spf(qb, e) + nqq : F_INF;
+      ok[e] = (sp[e] <= U[qb]) & (j < c1) & (j != q);
     }
-    *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 4 * g) = w[0];
-    *reinterpret_cast<f32x4*>(mlds + i16 * 32 + 16 + 4 * g) = w[1];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      float cs = mlds[(2 * c + half) * 32 + rel];
-      int cj = cs < F_INF ? t0 + rel : 0x7FFFFFFF;
-      sort32_asc(cs, cj, rel);
-      ls[qb * 8 + c] = cs;
-      lj[qb * 8 + c] = cj;
-      if (rel == kk - 1) mlds[512 + 2 * c + half] = cs;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const float Tk = mlds[512 + i16];
-    const float Un = (Tk - nqq) + band(Tk, __shfl(bcl0, qb * 16 + i16), __shfl(bcl1, qb * 16 + i16));
-    U[qb] = live ? Un : U[qb];
-    __builtin_amdgcn_wave_barrier();   // the scratch is rewritten for the next block
+    merge_block<CAPK>(ls, lj, U[qb], qb, sp, ok, nql, bcl0, bcl1, band, kk, t0, lane, g, i16, mlds);
   }
 }
 

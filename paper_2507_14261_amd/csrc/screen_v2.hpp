@@ -19,6 +19,11 @@ constexpr size_t v2_lds_bytes(int nkb) {
   return (size_t)PIPE * (V2Shape<NW>::BN * nkb * 64 + 4 * V2Shape<NW>::BN);
 }
 
+// Tiles at the start of each block's scan whose passing elements are merged
+// into the lists a query block at a time (merge_regs) rather than inserted
+// one by one.
+constexpr int V2_MERGE_TILES = 4;
+
 template <int PREC, int NKB, int NW>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
@@ -172,8 +177,9 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     }
   };
   // Screening filter of one group: lane holds rows t0h + jj*16 + 4g + r,
-  // query qb*16 + i16.
-  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h) {
+  // query qb*16 + i16.  MERGE: whole-block merges instead of single
+  // insertions (the first tiles of the scan).
+  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h, auto merge) __attribute__((always_inline)) {
     unsigned qbmask = 0;
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
@@ -182,10 +188,14 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
       for (int e = 1; e < 8; ++e) m = fminf(m, acc[qb][e >> 2][e & 3]);
       qbmask |= ballot(m <= U[qb]) ? (1u << qb) : 0u;
     }
-    if (qbmask)
-      insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk,
-                         [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; },
-                         t0h, bd.c1, wq0, lane, g, i16);
+    auto sv = [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; };
+    if (qbmask) {
+      if constexpr (decltype(merge)::value)
+        merge_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0h, bd.c1, wq0, lane, g, i16,
+                          iscratch[wave]);
+      else
+        insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0h, bd.c1, wq0, lane, g, i16);
+    }
   };
 
   // Software pipeline over 32-row groups: the products of the next group
@@ -201,25 +211,33 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   init_lists<QB>(ls, lj, U, nql, bcl0, bcl1, band, kk, [&](int qb, int e) { return accA[qb][e >> 2][e & 3]; },
                  bd.c0 + tstart * BN, bd.c1, wq0, lane, g, i16, iscratch[wave]);
   int tc = tstart;   // tile being computed
-  for (int it = 0; it < ntile; ++it) {
+  auto tile_step = [&](int it, auto merge) __attribute__((always_inline)) {
     const char* tile = smem + (it & (PIPE - 1)) * STG;
     const int t0 = bd.c0 + tc * BN;
     tc = tc + 1 == ntile ? 0 : tc + 1;
 #pragma unroll
     for (int h = 1; h < GR; h += 2) {
       products(tile, h, accB);
-      if (it > 0 || h > 1) filter(accA, t0 + 32 * (h - 1));
+      if (it > 0 || h > 1) filter(accA, t0 + 32 * (h - 1), merge);
       if (h + 1 < GR) {
         products(tile, h + 1, accA);
-        filter(accB, t0 + 32 * h);
+        filter(accB, t0 + 32 * h, merge);
       }
     }
     if (it + 1 < ntile) {
       next_tile(it + 1);
       products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
     }
-    filter(accB, t0 + 32 * (GR - 1));
+    filter(accB, t0 + 32 * (GR - 1), merge);
+  };
+  // the first tiles, where most rows still pass, merge whole blocks; the
+  // rest insert one element at a time
+  int it = 0;
+  if constexpr (NKB < 4) {   // at 4 K-blocks the merge's registers would spill
+    const int nmerge = min(ntile, V2_MERGE_TILES);
+    for (; it < nmerge; ++it) tile_step(it, std::true_type{});
   }
+  for (; it < ntile; ++it) tile_step(it, std::false_type{});
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 
   // ---- write the candidate lists and the bound of the rejected elements
