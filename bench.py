@@ -33,19 +33,19 @@ FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two f
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "560a8ce67fbfe05e91620fa531c8fe584433e953",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 968.465, "write_GB": 0.288,
+        "fetch_GB": 962.384, "write_GB": 0.292,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("rerank", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "860b25c13204c0c97e9571cd3adaeef3ecb8ffd6",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
                     "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5.268, "write_GB": 0.256,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("prep", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "860b25c13204c0c97e9571cd3adaeef3ecb8ffd6",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 0.512, "write_GB": 0.272,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
@@ -55,16 +55,16 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 1.704, "write_GB": 0.512,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "e8f4edaaaa9d978f1854ca9bbedf002c9b849509",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+        "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "393e7e925b916357258f66fec6deefacc2f2b964",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 2770.8, "write_GB": 0.130,
+        "fetch_GB": 2794.3, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dist_topk", "vmf-4m-d96"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "560a8ce67fbfe05e91620fa531c8fe584433e953",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "1d32be95821e313999db029dd46307e7bcd4870a",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 5785.4, "write_GB": 1.152,
+        "fetch_GB": 5771.1, "write_GB": 1.152,
         "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("exact_tree", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "2dde04c5ee757ec24b70d6ac123096784b61d10f",

@@ -232,10 +232,30 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   };
   // the first tiles, where most rows still pass, merge whole blocks; the
   // rest insert one element at a time
+  // At four K-blocks the merges run without the software pipeline (the
+  // products of a group, then its merge): the second accumulator set is not
+  // live across them, which keeps the merge's registers from spilling.
+  auto merge_step_serial = [&](int it) __attribute__((always_inline)) {
+    const char* tile = smem + (it & (PIPE - 1)) * STG;
+    const int t0 = bd.c0 + tc * BN;
+    tc = tc + 1 == ntile ? 0 : tc + 1;
+    if (it > 0) filter(accA, t0, std::true_type{});   // group 0 of the first tile filled the lists
+#pragma unroll
+    for (int h = 1; h < GR; ++h) {
+      products(tile, h, accA);
+      filter(accA, t0 + 32 * h, std::true_type{});
+    }
+    if (it + 1 < ntile) {
+      next_tile(it + 1);
+      products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
+    }
+  };
   int it = 0;
-  if constexpr (NKB < 4) {   // at 4 K-blocks the merge's registers would spill
-    const int nmerge = min(ntile, V2_MERGE_TILES);
+  const int nmerge = min(ntile, V2_MERGE_TILES);
+  if constexpr (NKB < 4) {
     for (; it < nmerge; ++it) tile_step(it, std::true_type{});
+  } else {
+    for (; it < nmerge; ++it) merge_step_serial(it);
   }
   for (; it < ntile; ++it) tile_step(it, std::false_type{});
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
