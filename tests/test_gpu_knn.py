@@ -295,6 +295,30 @@ def test_knn_batched_uneven_clouds_match_oracle(prec, d):
                                    atol=1e-6)
 
 
+# The first tiles of each block's scan merge their passing rows into the
+# lists a query block at a time (four 64-row tiles in the pipelined kernel,
+# without its software pipeline at four K-blocks; one 256-row tile in the
+# float8 streamed kernel); later rows are inserted one at a time.  Clouds
+# sized around those boundaries, with integer coordinates full of exact ties
+# (so the (s, j) order fixes every list), give exactly the oracle's lists in
+# every precision and kernel form.
+@pytest.mark.parametrize("prec,d", [("fp32", 24), ("fp32", 64), ("bf16", 24), ("bf16", 64), ("fp8", 24),
+                                    ("fp8", 96)])
+def test_knn_merged_first_tiles_boundaries_match_oracle(prec, d):
+    sizes = np.array([20, 32, 33, 255, 256, 257, 300, 511, 512, 513, 700])
+    X, offs = datagen.clouds(n_clouds=len(sizes), d=d, seed=d + 11, sizes=sizes)
+    X = np.round(X * 2.0).astype(np.float32)
+    k = 16
+    print(f"case merged-tiles {prec} d={d} sizes={sizes.tolist()}", flush=True)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True, offs=offs)
+    print("stats", st, flush=True)
+    for b in range(len(sizes)):
+        sl = slice(offs[b], offs[b + 1])
+        ref_n, ref_s = oracle.knn_exact(X[sl], k)
+        assert np.array_equal(nbr[sl] - offs[b], ref_n), (prec, d, b)
+        np.testing.assert_allclose(dist[sl], np.sqrt(ref_s), rtol=1e-6, atol=0)
+
+
 def test_knn_batched_integer_bf16_equals_fp32():
     sizes = np.array([5000, 333, 2700])
     X, offs = datagen.clouds(n_clouds=len(sizes), d=40, seed=17, sizes=sizes)
