@@ -34,15 +34,15 @@ FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two f
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
         "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 962.384, "write_GB": 0.292,
+        "fetch_GB": 964.664, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("rerank", "gamma-int-1m-d128"): {
         "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
                     "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 5.268, "write_GB": 0.256,
+        "fetch_GB": 5.267, "write_GB": 0.256,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("prep", "gamma-int-1m-d128"): {
         "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
@@ -56,15 +56,15 @@ MEASURED_TRAFFIC = {
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
         "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "393e7e925b916357258f66fec6deefacc2f2b964",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 2794.3, "write_GB": 0.130,
+        "fetch_GB": 2708.6, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dist_topk", "vmf-4m-d96"): {
         "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "cbcc9cf281794f3232b7e793a5641424920b39ad",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
-        "fetch_GB": 5771.1, "write_GB": 1.152,
+        "fetch_GB": 5764.2, "write_GB": 1.152,
         "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},
     ("exact_tree", "clouds-256-d64"): {
         "sources": {"paper_2507_14261_amd/csrc/mst.hip": "2dde04c5ee757ec24b70d6ac123096784b61d10f",

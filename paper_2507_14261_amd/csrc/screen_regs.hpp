@@ -90,12 +90,34 @@ struct Band {
 // and their last entries.
 constexpr int INIT_LDS_FLOATS = 16 * 32 + 32;
 
+// The value of lane (lane xor M) of the same half-wave, without the LDS
+// crossbar where the VALU can do it: DPP quad permutations for M = 1, 2;
+// for M = 4, 8 the row shifts by M in both directions (row_shl:M gives lane
+// i the value of lane i + M, row_shr:M that of lane i - M, both inside the
+// lane's row of 16), the lane's bit M choosing; ds_swizzle in bit-mask mode
+// (xor 16 within 32 lanes) for M = 16.
+template <int M>
+__device__ __forceinline__ int xor_lane32(int v, int rel) {
+  static_assert(M == 1 || M == 2 || M == 4 || M == 8 || M == 16, "a lane distance inside 32 lanes");
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+  } else if constexpr (M == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x401F);   // and 0x1F, or 0, xor 0x10
+  } else {
+    const int up = __builtin_amdgcn_update_dpp(0, v, 0x100 + M, 0xF, 0xF, false);   // row_shl:M
+    const int dn = __builtin_amdgcn_update_dpp(0, v, 0x110 + M, 0xF, 0xF, false);   // row_shr:M
+    return (rel & M) ? dn : up;
+  }
+}
+
 // Compare-exchange of (s, j) with the lane at distance M of the same
 // half-wave: where `asc`, the lower lane of the pair keeps the smaller key.
 template <int M>
 __device__ __forceinline__ void cex32(float& s, int& j, bool asc, int rel) {
-  const float ps = __shfl_xor(s, M);
-  const int pj = __shfl_xor(j, M);
+  const float ps = __int_as_float(xor_lane32<M>(__float_as_int(s), rel));
+  const int pj = xor_lane32<M>(j, rel);
   const bool lower = (rel & M) == 0;
   const bool pless = (ps < s) | ((ps == s) & (pj < j));
   const bool sless = (s < ps) | ((s == ps) & (j < pj));
