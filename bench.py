@@ -33,8 +33,8 @@ FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two f
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "578635b8a7d8fcc28f4ff529d74880d8a95efb27",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "f04dfe1780054e95ee03ac2c0b662a6271ae75f2",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 964.664, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
@@ -56,13 +56,13 @@ MEASURED_TRAFFIC = {
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("dist_topk", "lowrank-500k-d960"): {
         "sources": {"paper_2507_14261_amd/csrc/screen_hd.hpp": "393e7e925b916357258f66fec6deefacc2f2b964",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "f04dfe1780054e95ee03ac2c0b662a6271ae75f2",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 2708.6, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dist_topk", "vmf-4m-d96"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "44b61782d1092a28123218b4d535fe35911dd913",
-                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "c24a2cf518ff210f8beb4d6ef92e5213626c9324",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "578635b8a7d8fcc28f4ff529d74880d8a95efb27",
+                    "paper_2507_14261_amd/csrc/screen_regs.hpp": "f04dfe1780054e95ee03ac2c0b662a6271ae75f2",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5764.2, "write_GB": 1.152,
         "profile": "profiles/dist_topk_vmf-4m-d96_bf16_kernel_stats_and_hbm.md"},

@@ -335,6 +335,111 @@ __device__ __forceinline__ void merge_regs(LS& ls, LJ& lj, unsigned qbmask, floa
   }
 }
 
+// ------------------------------------------------ buffered list updates
+// Past the merged first tiles most groups pass a few elements per query
+// block.  Instead of one insertion pass each, they are appended to a
+// per-query LDS buffer of BUF_SLOTS (s, j) slots (bs, bj: query qi of the
+// wave owns slots BUF_SLOTS qi ..; empty slots hold +inf) under the
+// threshold of the block's last merge, and a block's buffers are merged
+// into its lists (flush_block) when one of them would overflow, and at the
+// end of the scan.  The threshold only tightens at merges, so more elements
+// are appended than the one-at-a-time rule would insert; every element the
+// filter rejects is still above the threshold in force, which never
+// increases, and every element a merge drops is at or above the list
+// maximum of that moment, so the certificate's bounds hold as before.
+constexpr int BUF_SLOTS = 16;
+
+template <class LS, class LJ>
+__device__ __forceinline__ void flush_block(LS& ls, LJ& lj, float& Uq, int qb, float* bs, int* bj, float nql,
+                                            float bcl0, float bcl1, const Band& band, int kk, int lane, int i16,
+                                            float* mlds) {
+  const int half = lane >> 5, rel = lane & 31;
+  const float nqq = __shfl(nql, qb * 16 + i16);
+#pragma unroll 1
+  for (int c = 0; c < 8; ++c) {
+    const int qi = qb * 16 + 2 * c + half;
+    float cs = rel < BUF_SLOTS ? bs[qi * BUF_SLOTS + rel] : F_INF;
+    int cj = rel < BUF_SLOTS ? bj[qi * BUF_SLOTS + rel] : 0x7FFFFFFF;
+    if (!(cs < F_INF)) cj = 0x7FFFFFFF;   // an empty slot
+    sort32<true>(cs, cj, rel);
+    const int L = qb * 8 + c;
+    const float os = ls[L];
+    const int oj = lj[L];
+    const bool cl = (cs < os) | ((cs == os) & (cj < oj));
+    float ms = cl ? cs : os;
+    int mj = cl ? cj : oj;
+    cex32<16>(ms, mj, true, rel);
+    cex32<8>(ms, mj, true, rel);
+    cex32<4>(ms, mj, true, rel);
+    cex32<2>(ms, mj, true, rel);
+    cex32<1>(ms, mj, true, rel);
+    ls[L] = ms;
+    lj[L] = mj;
+    if (rel == kk - 1) mlds[512 + 2 * c + half] = ms;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // empty the block's 16 x BUF_SLOTS slots: four per lane
+  static_assert(16 * BUF_SLOTS == 4 * 64, "four slots per lane");
+  *reinterpret_cast<f32x4*>(bs + qb * 16 * BUF_SLOTS + 4 * lane) = f32x4{F_INF, F_INF, F_INF, F_INF};
+  const float Tk = mlds[512 + i16];
+  const float Un = (Tk - nqq) + band(Tk, __shfl(bcl0, qb * 16 + i16), __shfl(bcl1, qb * 16 + i16));
+  Uq = Uq != -F_INF ? Un : Uq;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Appends of one 32-row group, in two halves of 16 rows (at most 16 passing
+// elements per query each, so a half always fits an emptied buffer).  A
+// lane's slot: its query's count, plus the passing elements of the same
+// query at lower elements of the half, plus those of lower lanes at its own
+// element (lanes i16, i16 + 16, i16 + 32, i16 + 48 hold one query).
+template <int QB, class LS, class LJ, class SpFn>
+__device__ __forceinline__ void buffer_regs(LS& ls, LJ& lj, unsigned qbmask, float (&U)[QB], int (&bc)[QB],
+                                            float* bs, int* bj, float nql, float bcl0, float bcl1,
+                                            const Band& band, int kk, SpFn spf, int t0, int c1, int wq0,
+                                            int lane, int g, int i16, float* mlds) {
+  const unsigned long long qm = 0x0001000100010001ull << i16;
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    if (!(qbmask & (1u << qb))) continue;
+    const int q = wq0 + qb * 16 + i16;
+    const float nqq = __shfl(nql, qb * 16 + i16);
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      float sp[4];
+      bool ok[4];
+      unsigned long long bl[4];
+      int n = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sp[r] = spf(qb, 4 * hh + r);
+        const int j = t0 + 16 * hh + 4 * g + r;
+        ok[r] = (sp[r] <= U[qb]) & (j < c1) & (j != q);
+        bl[r] = ballot(ok[r]);
+        n += __builtin_popcountll(bl[r] & qm);
+      }
+      if ((bl[0] | bl[1] | bl[2] | bl[3]) == 0) continue;
+      if (ballot(bc[qb] + n > BUF_SLOTS)) {
+        flush_block(ls, lj, U[qb], qb, bs, bj, nql, bcl0, bcl1, band, kk, lane, i16, mlds);
+        bc[qb] = 0;
+      }
+      int base = bc[qb];
+      float* rs = bs + (qb * 16 + i16) * BUF_SLOTS;
+      int* rj = bj + (qb * 16 + i16) * BUF_SLOTS;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (ok[r]) {
+          const int slot = base + __builtin_popcountll(bl[r] & qm & below);
+          rs[slot] = sp[r] + nqq;
+          rj[slot] = t0 + 16 * hh + 4 * g + r;
+        }
+        base += __builtin_popcountll(bl[r] & qm);
+      }
+      bc[qb] = base;
+    }
+  }
+}
+
 // A query fragment (8 bf16 or 4 float32 values) times -2; exact for every
 // finite input (a power-of-two scaling, far from overflow for rows that
 // passed the norm check).

@@ -38,6 +38,11 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ __attribute__((aligned(16))) float iscratch[NW][INIT_LDS_FLOATS];   // lists from the first rows
+  // buffered list updates past the merged tiles (up to two K-blocks: beyond,
+  // the ring leaves no LDS for them at two blocks per CU)
+  constexpr bool BUFD = NKB <= 2;
+  __shared__ __attribute__((aligned(16))) float bufs[BUFD ? NW : 1][BUFD ? 64 * BUF_SLOTS : 4];
+  __shared__ __attribute__((aligned(16))) int bufj[BUFD ? NW : 1][BUFD ? 64 * BUF_SLOTS : 4];
 
   const BlockDesc bd = desc[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -81,6 +86,14 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   for (int L = 0; L < 32; ++L) {
     ls[L] = F_INF;
     lj[L] = 0x7FFFFFFF;
+  }
+  int bcnt[QB];   // buffered elements of the lane's query in each block
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) bcnt[qb] = 0;
+  if constexpr (BUFD) {
+#pragma unroll
+    for (int i = 0; i < BUF_SLOTS / 4; ++i)
+      *reinterpret_cast<f32x4*>(&bufs[wave][BUF_SLOTS * lane + 4 * i]) = f32x4{F_INF, F_INF, F_INF, F_INF};
   }
 
   // Loads of a tile into a stage: chunk slot p of the stage holds chunk
@@ -190,9 +203,13 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     }
     auto sv = [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; };
     if (qbmask) {
-      if constexpr (decltype(merge)::value)
+      constexpr int mode = (int)decltype(merge)::value;   // 0 single, 1 merged, 2 buffered
+      if constexpr (mode == 1)
         merge_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0h, bd.c1, wq0, lane, g, i16,
                           iscratch[wave]);
+      else if constexpr (mode == 2)
+        buffer_regs<QB>(ls, lj, qbmask, U, bcnt, bufs[wave], bufj[wave], nql, bcl0, bcl1, band, kk, sv, t0h,
+                        bd.c1, wq0, lane, g, i16, iscratch[wave]);
       else
         insert_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0h, bd.c1, wq0, lane, g, i16);
     }
@@ -257,7 +274,17 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   } else {
     for (; it < nmerge; ++it) merge_step_serial(it);
   }
-  for (; it < ntile; ++it) tile_step(it, std::false_type{});
+  if constexpr (BUFD) {
+    // the rest of the scan appends to the buffers; the last merge empties them
+    for (; it < ntile; ++it) tile_step(it, std::integral_constant<int, 2>{});
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb)
+      if (ballot(bcnt[qb] > 0))
+        flush_block(ls, lj, U[qb], qb, bufs[wave], bufj[wave], nql, bcl0, bcl1, band, kk, lane, i16,
+                    iscratch[wave]);
+  } else {
+    for (; it < ntile; ++it) tile_step(it, std::false_type{});
+  }
   wait_vmcnt<0>();   // no load may land in LDS after the block ends
 
   // ---- write the candidate lists and the bound of the rejected elements
