@@ -190,9 +190,9 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     }
   };
   // Screening filter of one group: lane holds rows t0h + jj*16 + 4g + r,
-  // query qb*16 + i16.  MERGE: whole-block merges instead of single
-  // insertions (the first tiles of the scan).
-  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h, auto merge) __attribute__((always_inline)) {
+  // query qb*16 + i16.  The mode (a compile-time constant) picks the list
+  // update: 0 single insertions, 1 whole-block merges, 2 buffered appends.
+  auto filter = [&](const f32x4 (&acc)[QB][2], int t0h, auto mode) __attribute__((always_inline)) {
     unsigned qbmask = 0;
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
@@ -203,11 +203,11 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     }
     auto sv = [&](int qb, int e) { return acc[qb][e >> 2][e & 3]; };
     if (qbmask) {
-      constexpr int mode = (int)decltype(merge)::value;   // 0 single, 1 merged, 2 buffered
-      if constexpr (mode == 1)
+      constexpr int m = (int)decltype(mode)::value;
+      if constexpr (m == 1)
         merge_regs<QB, 8>(ls, lj, qbmask, U, nql, bcl0, bcl1, band, kk, sv, t0h, bd.c1, wq0, lane, g, i16,
                           iscratch[wave]);
-      else if constexpr (mode == 2)
+      else if constexpr (m == 2)
         buffer_regs<QB>(ls, lj, qbmask, U, bcnt, bufs[wave], bufj[wave], nql, bcl0, bcl1, band, kk, sv, t0h,
                         bd.c1, wq0, lane, g, i16, iscratch[wave]);
       else
@@ -228,27 +228,25 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   init_lists<QB>(ls, lj, U, nql, bcl0, bcl1, band, kk, [&](int qb, int e) { return accA[qb][e >> 2][e & 3]; },
                  bd.c0 + tstart * BN, bd.c1, wq0, lane, g, i16, iscratch[wave]);
   int tc = tstart;   // tile being computed
-  auto tile_step = [&](int it, auto merge) __attribute__((always_inline)) {
+  auto tile_step = [&](int it, auto mode) __attribute__((always_inline)) {
     const char* tile = smem + (it & (PIPE - 1)) * STG;
     const int t0 = bd.c0 + tc * BN;
     tc = tc + 1 == ntile ? 0 : tc + 1;
 #pragma unroll
     for (int h = 1; h < GR; h += 2) {
       products(tile, h, accB);
-      if (it > 0 || h > 1) filter(accA, t0 + 32 * (h - 1), merge);
+      if (it > 0 || h > 1) filter(accA, t0 + 32 * (h - 1), mode);
       if (h + 1 < GR) {
         products(tile, h + 1, accA);
-        filter(accB, t0 + 32 * h, merge);
+        filter(accB, t0 + 32 * h, mode);
       }
     }
     if (it + 1 < ntile) {
       next_tile(it + 1);
       products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
     }
-    filter(accB, t0 + 32 * (GR - 1), merge);
+    filter(accB, t0 + 32 * (GR - 1), mode);
   };
-  // the first tiles, where most rows still pass, merge whole blocks; the
-  // rest insert one element at a time
   // At four K-blocks the merges run without the software pipeline (the
   // products of a group, then its merge): the second accumulator set is not
   // live across them, which keeps the merge's registers from spilling.
@@ -267,6 +265,10 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
       products(smem + ((it + 1) & (PIPE - 1)) * STG, 0, accA);
     }
   };
+  // The scan runs in phases, each its own copy of the tile loop, so that the
+  // list registers have one update path per loop: the first tiles, where
+  // most rows still pass, merge whole query blocks; the rest append to the
+  // LDS buffers (up to two K-blocks) or insert one element at a time.
   int it = 0;
   const int nmerge = min(ntile, V2_MERGE_TILES);
   if constexpr (NKB < 4) {
