@@ -319,6 +319,33 @@ def test_knn_merged_first_tiles_boundaries_match_oracle(prec, d):
         np.testing.assert_allclose(dist[sl], np.sqrt(ref_s), rtol=1e-6, atol=0)
 
 
+# Past the merged tiles the one- and two-K-block kernels append passing
+# elements to per-query LDS buffers and merge them when one would overflow:
+# clouds of 300-3000 points with every row repeated three times (exact
+# zero-distance ties) and integer coordinates in a small range (many equal
+# distances) overflow the buffers often; the lists must still be exactly
+# the oracle's (s, j)-ordered kNN.
+@pytest.mark.parametrize("prec,d", [("fp32", 16), ("fp32", 32), ("bf16", 32), ("bf16", 64)])
+def test_knn_buffered_updates_with_duplicates_match_oracle(prec, d):
+    rng = np.random.default_rng(d + 101)
+    sizes = np.array([300, 1203, 3000, 777])
+    parts = []
+    for m in sizes:
+        base = rng.integers(-3, 4, size=(int(m) // 3 + 1, d)).astype(np.float32)
+        parts.append(np.repeat(base, 3, axis=0)[rng.permutation(3 * len(base))][: int(m)])
+    X = np.concatenate(parts)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    k = 16
+    print(f"case buffered-dups {prec} d={d} sizes={sizes.tolist()}", flush=True)
+    nbr, dist, st = _run(X, k, precision=prec, exact=True, offs=offs)
+    print("stats", st, flush=True)
+    for b in range(len(sizes)):
+        sl = slice(offs[b], offs[b + 1])
+        ref_n, ref_s = oracle.knn_exact(X[sl], k)
+        assert np.array_equal(nbr[sl] - offs[b], ref_n), (prec, d, b)
+        np.testing.assert_allclose(dist[sl], np.sqrt(ref_s), rtol=1e-6, atol=0)
+
+
 def test_knn_batched_integer_bf16_equals_fp32():
     sizes = np.array([5000, 333, 2700])
     X, offs = datagen.clouds(n_clouds=len(sizes), d=40, seed=17, sizes=sizes)
