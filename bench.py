@@ -33,19 +33,19 @@ FP32_VALU_TFLOPS = 157.3   # vector float32, fused multiply-add counted as two f
 # change.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
     ("dist_topk", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "ab898d884c01cfaf8a7f50a00b88091883800643",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "8b27565b9dff0b55176140ed5ecb7a42c316bec8",
                     "paper_2507_14261_amd/csrc/screen_regs.hpp": "f04dfe1780054e95ee03ac2c0b662a6271ae75f2",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 964.664, "write_GB": 0.288,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("rerank", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "8938109143edc6833afe2c1ff2ce25193d51c410",
                     "paper_2507_14261_amd/csrc/select.hpp": "a8e57a59a59aa64045df243bd780742f4798e2db",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5.267, "write_GB": 0.256,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
     ("prep", "gamma-int-1m-d128"): {
-        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "e7532dbf9ae7ca336360e806fca51ddd4d8cd166",
+        "sources": {"paper_2507_14261_amd/csrc/knn.hip": "8938109143edc6833afe2c1ff2ce25193d51c410",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 0.512, "write_GB": 0.272,
         "profile": "profiles/dist_topk_gamma-int-1m-d128_bf16_hbm_counters.md"},
@@ -61,7 +61,7 @@ MEASURED_TRAFFIC = {
         "fetch_GB": 2708.6, "write_GB": 0.130,
         "profile": "profiles/dist_topk_lowrank-500k-d960_kernel_stats_and_hbm.md"},
     ("dist_topk", "vmf-4m-d96"): {
-        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "ab898d884c01cfaf8a7f50a00b88091883800643",
+        "sources": {"paper_2507_14261_amd/csrc/screen_v2.hpp": "8b27565b9dff0b55176140ed5ecb7a42c316bec8",
                     "paper_2507_14261_amd/csrc/screen_regs.hpp": "f04dfe1780054e95ee03ac2c0b662a6271ae75f2",
                     "paper_2507_14261_amd/csrc/famst_common.hpp": "38cc843bdab55bea9b6987a1878e69497774fc7e"},
         "fetch_GB": 5764.2, "write_GB": 1.152,

@@ -1014,6 +1014,7 @@ struct KnnPlan {
   bool chunked;   // K-chunked kernel (any d, float8) instead of resident queries
   bool piped;     // register lists + pipelined tiles (k' = 32, up to 128 bf16 / 64 fp32 dims)
   bool hd;        // register lists, queries and rows streamed by K-steps (k' = 32, beyond 128 dims)
+  bool buffered;  // pipelined kernel with buffered list updates (short scans, up to two K-blocks)
   size_t lds;
 };
 
@@ -1036,6 +1037,11 @@ static constexpr int64_t SPATIAL_MIN = 4096;
 // longest (4M x 96: 9 % faster) but not at 1M x 128 (15 % slower: the wider
 // barrier leaves a compute unit idle more often)
 static constexpr int64_t V2_WIDE_MIN = 2097152;
+// Largest cloud whose screening scan buffers its list updates: on longer
+// scans under a spatial order few rows pass after the first tiles, and single
+// insertions cost less than the buffered loop (1M x 32 bf16: 119.5 against
+// 130.8 ms; 200K x 32: 10.6 against 10.8 ms; 10K x 32: 1.29 against 1.80 ms).
+static constexpr int64_t V2_BUF_MAX_ROWS = 32768;
 
 static int choose_plan(int prec, int d, int k, int k_cand, int64_t nmax, KnnPlan& p) {
   p.nw = 4;
@@ -1049,6 +1055,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, int64_t nmax, KnnPlan
   p.chunked = prec == FAMST_FP8_E4M3 || p.nkb > 8;
   p.piped = false;
   p.hd = false;
+  p.buffered = false;
   // beyond the register-resident queries (for float32 beyond 64 dims, where
   // the streamed operands cost less than the LDS-list kernel's waits; for
   // float8 at any d)
@@ -1068,6 +1075,7 @@ static int choose_plan(int prec, int d, int k, int k_cand, int64_t nmax, KnnPlan
     if (p.KC == 32 && p.nkb <= 4) {
       p.piped = true;
       p.nw = nmax >= V2_WIDE_MIN ? 8 : 4;
+      p.buffered = p.nw == 4 && p.nkb <= 2 && nmax <= V2_BUF_MAX_ROWS;
       p.qblk = 64 * p.nw;
       p.lds = p.nw == 8 ? v2_lds_bytes<8>(p.nkb) : v2_lds_bytes<4>(p.nkb);
     }
@@ -1131,10 +1139,10 @@ struct BandArgs {
   const int* perm;   // spatial order of the rows of Xq (null: identity)
 };
 
-template <int PREC, int NKB, int NW>
+template <int PREC, int NKB, int NW, bool BUF = false>
 static int launch_v2(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq, const float* nq,
                      const BlockDesc* desc, int* cj, float* cs, const BandArgs& ba) {
-  auto kern = dist_topk_v2_kernel<PREC, NKB, NW>;
+  auto kern = dist_topk_v2_kernel<PREC, NKB, NW, BUF>;
   // the kernel also holds static LDS (the list-initialisation scratch): ask
   // for exactly the dynamic bytes this launch uses
   static size_t attr = 0;
@@ -1171,14 +1179,20 @@ static int dispatch_dt(const KnnPlan& p, int nblk, hipStream_t s, const void* Xq
   case NKB:                                                                                                 \
     return p.nw == 8 ? launch_v2<PREC, NKB, 8>(p, nblk, s, Xq, nq, desc, cj, cs, ba)                       \
                      : launch_v2<PREC, NKB, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
+#define V2_CASE_BUF(NKB)                                                                                    \
+  case NKB:                                                                                                 \
+    return p.nw == 8 ? launch_v2<PREC, NKB, 8>(p, nblk, s, Xq, nq, desc, cj, cs, ba)                       \
+           : p.buffered ? launch_v2<PREC, NKB, 4, true>(p, nblk, s, Xq, nq, desc, cj, cs, ba)               \
+                        : launch_v2<PREC, NKB, 4>(p, nblk, s, Xq, nq, desc, cj, cs, ba);
     switch (p.nkb) {
-      V2_CASE(1)
-      V2_CASE(2)
+      V2_CASE_BUF(1)
+      V2_CASE_BUF(2)
       V2_CASE(3)
       V2_CASE(4)
       default: return FAMST_ENOTIMPL;
     }
 #undef V2_CASE
+#undef V2_CASE_BUF
   }
 #define DT_CASE(NKB)                                                                        \
   if (p.nkb <= NKB) {                                                                       \

@@ -24,7 +24,11 @@ constexpr size_t v2_lds_bytes(int nkb) {
 // one by one.
 constexpr int V2_MERGE_TILES = 4;
 
-template <int PREC, int NKB, int NW>
+// BUF: the scan past the merged tiles appends to per-query LDS buffers
+// (buffer_regs) instead of inserting one element at a time; for four-wave
+// blocks of up to two K-blocks (beyond, the ring leaves no LDS for the
+// buffers at two blocks per CU), chosen by the host for short scans.
+template <int PREC, int NKB, int NW, bool BUF = false>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
     const void* __restrict__ Xq_, const float* __restrict__ nq, int nkb,
     const BlockDesc* __restrict__ desc, int* __restrict__ cand_j, float* __restrict__ cand_s,
@@ -38,9 +42,9 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   const char* Xb = reinterpret_cast<const char*>(Xq_);
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ __attribute__((aligned(16))) float iscratch[NW][INIT_LDS_FLOATS];   // lists from the first rows
-  // buffered list updates past the merged tiles (up to two K-blocks: beyond,
-  // the ring leaves no LDS for them at two blocks per CU)
-  constexpr bool BUFD = NKB <= 2;
+  // buffered list updates past the merged tiles
+  static_assert(!BUF || (NKB <= 2 && NW == 4), "buffers only where the LDS holds them");
+  constexpr bool BUFD = BUF;
   __shared__ __attribute__((aligned(16))) float bufs[BUFD ? NW : 1][BUFD ? 64 * BUF_SLOTS : 4];
   __shared__ __attribute__((aligned(16))) int bufj[BUFD ? NW : 1][BUFD ? 64 * BUF_SLOTS : 4];
 
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void dist_topk_v2_kernel(
   // The scan runs in phases, each its own copy of the tile loop, so that the
   // list registers have one update path per loop: the first tiles, where
   // most rows still pass, merge whole query blocks; the rest append to the
-  // LDS buffers (up to two K-blocks) or insert one element at a time.
+  // LDS buffers (BUF) or insert one element at a time.
   int it = 0;
   const int nmerge = min(ntile, V2_MERGE_TILES);
   if constexpr (NKB < 4) {
